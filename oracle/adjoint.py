@@ -1,0 +1,107 @@
+"""FP64 gradients of the forward march (oracle, test infrastructure).
+
+The paper trains end to end through the ray marcher and notes that the
+additive accumulation rule, unlike the multiplicative one, lets the backward
+pass avoid storing the full graph of per-sample operations (Sec. 3.2.2); its
+details are in a supplemental document that is not available.  The adjoint
+below is derived directly from the forward of ``render.py``.
+
+Per ray, let dL/dI = g (3-vector) and dL/dA = h.  Let S be the clamping
+sample if the clamp was hit (then A = 1 and T_{S-1} is the opacity before it).
+Define the constant
+    Tdot = h                 if the clamp was not hit,
+    Tdot = -g . (C_S/sigma_S) if it was.
+For every processed sample j other than S and every primitive k containing it:
+    dL/dsigma_kj = dt (Tdot + g . c_kj),        dL/dc_kj = dt sigma_kj g
+and at S:
+    dL/dsigma_kS = (1 - T_{S-1}) g . (c_kS - C_S/sigma_S) / sigma_S,
+    dL/dc_kS     = (1 - T_{S-1}) (sigma_kS / sigma_S) g.
+Samples after the stop contribute nothing.  The early-stop decision and box
+membership are piecewise constant and carry no gradient.
+
+The channel adjoints flow to the 8 payload corners through the trilinear
+weights, and to the pose through the local coordinate
+y = A (x - t), A = diag(1/s) R^T, x = o + tau d:
+    dL/dt = -A^T g_y,   dL/dR_mi = g_y,i (x_m - t_m) / s_i,   dL/ds_i = -g_y,i y_i / s_i
+where g_y = sum over channels of (channel adjoint) * d(channel)/dy.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .render import render
+
+F64 = np.float64
+
+
+def render_grad(prims, cam, params, grad_rgba, pixels=None, geometry="fp32"):
+    """Forward of ``render`` plus the gradient of L = sum(grad_rgba * rgba).
+
+    Returns (forward dict, grads) where grads has
+      payload [N,M,M,M,4], pos [N,3], rot [N,3,3], scale [N,3]  (FP64)."""
+    out = render(prims, cam, params, pixels, geometry, _want_grad=True)
+    A32, tr, g_sig, g_col, rb, last_group = out.pop("_internal")
+    n, M = prims.n, prims.m
+    gpay = np.zeros(n * M * M * M * 4)
+    gpos = np.zeros((n, 3))
+    grot = np.zeros((n, 3, 3))
+    gscale = np.zeros((n, 3))
+    grads = {"payload": gpay, "pos": gpos, "rot": grot, "scale": gscale}
+    R = out["rgba"].shape[0]
+    gr = np.asarray(grad_rgba, dtype=F64).reshape(R, 4)
+    ntr = tr["ray"].size
+    if ntr == 0:
+        grads["payload"] = gpay.reshape(n, M, M, M, 4)
+        return out, grads
+    dt = float(params.step)
+
+    # per-ray constants
+    sat = out["t_prev"] >= 0
+    tdot = gr[:, 3].copy()
+    cbar = np.zeros((R, 3))
+    sig_s = np.ones(R)
+    for r in np.nonzero(sat)[0]:
+        s = last_group[r]
+        sig_s[r] = g_sig[s]
+        cbar[r] = g_col[s] / g_sig[s]
+        tdot[r] = -float(gr[r, :3] @ cbar[r])
+
+    ray = tr["ray"]
+    g = gr[ray, :3]
+    val = tr["val"]
+    c, sig = val[:, :3], val[:, 3]
+    used = tr["group"] <= last_group[ray]
+    at_s = sat[ray] & (tr["group"] == last_group[ray])
+    regular = used & ~at_s
+
+    adj = np.zeros((ntr, 4))
+    gc_dot = np.einsum("ij,ij->i", g, c)
+    adj[regular, 3] = dt * (tdot[ray][regular] + gc_dot[regular])
+    adj[regular, :3] = dt * sig[regular, None] * g[regular]
+    if np.any(at_s):
+        w = (1.0 - out["t_prev"][ray][at_s])
+        ss = sig_s[ray][at_s]
+        adj[at_s, 3] = w * np.einsum("ij,ij->i", g[at_s], c[at_s] - cbar[ray][at_s]) / ss
+        adj[at_s, :3] = (w * sig[at_s] / ss)[:, None] * g[at_s]
+
+    # payload: through the trilinear weights
+    for corner in range(8):
+        base = tr["corner_idx"][:, corner] * 4
+        wgt = tr["corner_w"][:, corner]
+        for ch in range(4):
+            np.add.at(gpay, base + ch, wgt * adj[:, ch])
+    grads["payload"] = gpay.reshape(n, M, M, M, 4)
+
+    # pose: through y = diag(1/s) R^T (o + tau d - t)
+    gy = np.einsum("ic,icd->id", adj, tr["dval"])                    # [ntr,3]
+    k = tr["prim"]
+    pos = prims.pos.astype(F64)
+    rot = prims.rot.astype(F64)
+    s = prims.scale.astype(F64)
+    A = np.swapaxes(rot, -1, -2) / s[:, :, None]
+    d = out["dirs"].astype(F64)[ray]
+    xt = (np.asarray(cam.origin, dtype=F64)[None, :] - pos[k]) + tr["tau"][:, None] * d
+    np.add.at(gpos, k, -np.einsum("nij,ni->nj", A[k], gy))
+    np.add.at(grot, k, xt[:, :, None] * (gy / s[k])[:, None, :])
+    np.add.at(gscale, k, -gy * tr["y"] / s[k])
+    return out, grads
