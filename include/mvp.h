@@ -1,0 +1,219 @@
+/*
+ * mvp.h - C ABI of the MI355X ray marcher for mixtures of volumetric primitives.
+ *
+ * The library renders images of a set of oriented voxel primitives
+ * (Lombardi et al., "Mixture of Volumetric Primitives for Efficient Neural
+ * Rendering", ACM TOG 40(4), 2021) and differentiates them:
+ *
+ *   - a primitive k is {t_k, R_k, s_k, V_k}: position, rotation, per-axis scale
+ *     and an RGBA payload grid of M^3 voxels; t, R and s form its
+ *     model-to-world transform (Sec. 3.1.2);
+ *   - a pixel ray r(t) = o + t d is marched at fixed world-space steps, only
+ *     against the primitives it intersects, between the first entry and the
+ *     last exit (Sec. 3.2.1);
+ *   - colour and opacity are accumulated front to back with the additive,
+ *     clamped rule I = int V_col dT, T = min(int V_alpha, 1), A = T(t_max),
+ *     stopping once T > 1 - eps_early (Sec. 3.2.2).
+ *
+ * Conventions (all calls):
+ *   - Pointers are DEVICE pointers unless marked "host".  The caller owns every
+ *     buffer it passes; the library never frees them.  The library owns
+ *     contexts, acceleration structures and resident serving scenes.
+ *   - Work is enqueued on the given HIP stream (hipStream_t passed as void*;
+ *     NULL is the null stream) and returns without waiting, except where a
+ *     call says it blocks.
+ *   - Argument errors return MVP_ERR_INVALID synchronously and enqueue nothing.
+ *     A failed HIP call returns MVP_ERR_DEVICE; out-of-memory returns
+ *     MVP_ERR_OOM.  mvp_last_error() then holds a message.  No C++ exception
+ *     crosses this boundary.
+ *   - Preconditions not checked on the device: payload values finite with
+ *     opacity >= 0, scales > 0, rotations finite.
+ */
+#ifndef MVP_H
+#define MVP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MVP_OK = 0,
+  MVP_ERR_INVALID = 1,   /* bad argument, unknown handle or ticket            */
+  MVP_ERR_OOM = 2,       /* device memory or the serving budget is exhausted   */
+  MVP_ERR_DEVICE = 3,    /* a HIP call failed                                  */
+  MVP_ERR_BUSY = 4,      /* resource still in use by in-flight work            */
+  MVP_ERR_NOT_READY = 5  /* result not available yet                          */
+} mvp_status;
+
+typedef enum { MVP_F32 = 0, MVP_BF16 = 1 } mvp_dtype;
+
+typedef struct mvp_ctx mvp_ctx;       /* device, memory cache, serving scheduler */
+typedef struct mvp_accel mvp_accel;   /* per-frame culling lists and ray/primitive intervals */
+
+/* The primitives {t_k, R_k, s_k, V_k} (Sec. 3.1.2).  All device pointers.
+ *   pos     [N,3]        float32  t_k, world position of the box centre
+ *   rot     [N,3,3]      float32  R_k row-major, local-to-world: x = R diag(s) y + t,
+ *                                 y in the closed local box [-1,1]^3
+ *   scale   [N,3]        float32  s_k > 0, half extent of the box along each local axis
+ *   payload [N,M,M,M,4]  float32 or bf16 (payload_dtype), index [k][iz][iy][ix][c],
+ *                                 c = (R,G,B,opacity density); voxel i of an axis sits
+ *                                 at local coordinate -1 + 2i/(M-1); 16-byte aligned
+ *                                 (8-byte for bf16).
+ * n_prim == 0 is legal and renders an empty image. */
+typedef struct {
+  int32_t n_prim;
+  int32_t M;               /* >= 2 */
+  int32_t payload_dtype;   /* mvp_dtype */
+  int32_t reserved;
+  const float *pos;
+  const float *rot;
+  const float *scale;
+  const void *payload;
+} mvp_prims;
+
+/* Pinhole camera (Sec. 4.1), a HOST struct.  The ray of pixel (px, py) starts at
+ * origin and points along pix2dir @ (px + 0.5, py + 0.5, 1), normalised to unit
+ * length so that t is world distance. */
+typedef struct {
+  int32_t width, height;
+  float origin[3];
+  float pix2dir[9];        /* row-major 3x3 */
+} mvp_camera;
+
+/* March parameters: sample j sits at t = j * step (step > 0); the march stops
+ * after a sample once the accumulated opacity exceeds 1 - eps_early
+ * (0 <= eps_early < 1, Sec. 3.2.2); only t >= t_near >= 0 is integrated. */
+typedef struct {
+  float step;
+  float eps_early;
+  float t_near;
+} mvp_march_params;
+
+/* Per-ray state the forward leaves for the backward: the index of the last
+ * sample processed (-1 if the ray met no sample) and, if the clamp
+ * T = min(., 1) was hit at that sample, the opacity just before it (else -1). */
+typedef struct {
+  int32_t j_end;
+  float t_prev;
+} mvp_ray_aux;
+
+/* Sizes of an acceleration structure (host struct). */
+typedef struct {
+  int32_t n_views, width, height, n_prim;
+  int64_t n_tile_pairs;    /* (tile, primitive) entries of the culling lists           */
+  int64_t n_ray_pairs;     /* (ray, primitive) pairs with at least one sample           */
+  int64_t device_bytes;    /* device memory held by the structure                       */
+} mvp_accel_info;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`. */
+mvp_status mvp_create(int device, mvp_ctx **out);
+/* Destroy a context.  Waits for its serving work; fails with MVP_ERR_BUSY if an
+ * acceleration structure created from it is still alive. */
+mvp_status mvp_destroy(mvp_ctx *ctx);
+/* Message of the last failed call on this thread; never NULL. */
+const char *mvp_last_error(void);
+/* Library version string; never NULL. */
+const char *mvp_version(void);
+
+/* ---- rendering (Sec. 3.2) ------------------------------------------------- */
+
+/* Per-frame acceleration structure for n_views cameras of one resolution:
+ * screen-tile culling lists of the primitives (the role the paper's per-frame
+ * BVH plays, Sec. 3.2.1), then for every ray the primitives it intersects and
+ * the fixed-step sample interval inside each (the ray-specific lists and
+ * domain of integration of Sec. 3.2.1).  cams is a HOST array of n_views.
+ * Reads prims->pos/rot/scale; the payload is not read.  BLOCKS until the list
+ * sizes are known (two stream synchronisations).  *out must be released with
+ * mvp_accel_destroy. */
+mvp_status mvp_build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams,
+                           int32_t n_views, const mvp_march_params *params,
+                           mvp_accel **out, void *stream);
+/* Release an acceleration structure.  Its memory is recycled only after the
+ * work already enqueued on `stream` has finished. */
+mvp_status mvp_accel_destroy(mvp_ctx *ctx, mvp_accel *accel, void *stream);
+mvp_status mvp_accel_get_info(const mvp_accel *accel, mvp_accel_info *info);
+
+/* Forward march (Sec. 3.2.2).  prims must be the primitives the structure was
+ * built from (payload may differ).  Writes
+ *   rgba [n_views,H,W,4] float32: premultiplied colour I and alpha A per pixel,
+ *   aux  [n_views,H,W]   mvp_ray_aux (may be NULL if no backward follows).
+ * Deterministic: each pixel is written by one thread in a fixed order. */
+mvp_status mvp_render_fwd(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims *prims,
+                          float *rgba, mvp_ray_aux *aux, void *stream);
+
+/* Backward of mvp_render_fwd for L with dL/drgba = grad_rgba [n_views,H,W,4]
+ * float32, using the aux of the same forward.  ACCUMULATES (+=) into
+ *   grad_payload [N,M,M,M,4] float32 (also for bf16 payloads),
+ *   grad_pos [N,3], grad_rot [N,3,3], grad_scale [N,3] float32;
+ * any of the four may be NULL to skip it.  Uses device atomics, so the order
+ * of floating-point additions (not the math) varies between runs. */
+mvp_status mvp_render_bwd(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims *prims,
+                          const mvp_ray_aux *aux, const float *grad_rgba,
+                          float *grad_payload, float *grad_pos, float *grad_rot,
+                          float *grad_scale, void *stream);
+
+/* Sample counts of the most recent forward on this structure (BLOCKS on
+ * `stream`): ray-samples (samples inside >= 1 intersected primitive, up to the
+ * early stop) and prim-samples ((sample, primitive) pairs, i.e. trilinear
+ * payload fetches). */
+mvp_status mvp_accel_counts(mvp_ctx *ctx, const mvp_accel *accel, uint64_t *ray_samples,
+                            uint64_t *prim_samples, void *stream);
+
+/* Hit sets for testing: for every ray, the ids of the primitives its ray
+ * intersects (slab test only, including hits with no sample), ascending.
+ * offsets [n_rays+1] int64 and ids [ids_cap] int32 are device buffers; if the
+ * total exceeds ids_cap, *n_total is set and MVP_ERR_OOM returned (offsets are
+ * still written).  BLOCKS on `stream`. */
+mvp_status mvp_debug_hits(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims *prims,
+                          int64_t *offsets, int32_t *ids, int64_t ids_cap, int64_t *n_total,
+                          void *stream);
+
+/* ---- serving: resident scenes and continuous batching ----------------------- */
+
+/* Configure the serving scheduler: device memory budget (resident scenes plus
+ * in-flight request scratch) and number of concurrent request slots (each
+ * with its own stream).  Must be called before the first scene is created. */
+mvp_status mvp_serve_configure(mvp_ctx *ctx, size_t budget_bytes, int32_t n_slots);
+
+/* Copy a scene (device pointers in *src) into library-owned device memory that
+ * stays resident until released.  Counts against the budget (MVP_ERR_OOM). */
+mvp_status mvp_scene_create(mvp_ctx *ctx, const mvp_prims *src, uint64_t *scene_id);
+/* Release a resident scene; MVP_ERR_BUSY while requests on it are pending. */
+mvp_status mvp_scene_release(mvp_ctx *ctx, uint64_t scene_id);
+
+/* One render request: a resident scene seen from one camera.  rgba_out is a
+ * caller-owned device buffer [H,W,4] float32 that must stay valid until the
+ * request completes. */
+typedef struct {
+  uint64_t scene_id;
+  mvp_camera cam;
+  mvp_march_params params;
+  float *rgba_out;
+} mvp_request;
+
+/* Queue a request; never blocks.  The scheduler admits queued requests in
+ * arrival order as soon as a slot is free and the request's scratch memory
+ * fits in the budget, and runs admitted requests concurrently on their slot
+ * streams.  A request larger than the whole budget fails at admission. */
+mvp_status mvp_submit(mvp_ctx *ctx, const mvp_request *req, uint64_t *ticket);
+
+/* Request state: *state = 0 queued, 1 running, 2 done, 3 failed.  Times are
+ * seconds on a monotonic clock (submission, and completion of the GPU work;
+ * completion 0 until done).  A done/failed ticket stays queryable until
+ * mvp_ticket_release.  Unknown ticket: MVP_ERR_INVALID. */
+mvp_status mvp_poll(mvp_ctx *ctx, uint64_t ticket, int32_t *state, double *t_submit,
+                    double *t_done);
+/* Block until the ticket is done or failed, or timeout_s elapses
+ * (MVP_ERR_NOT_READY). */
+mvp_status mvp_wait(mvp_ctx *ctx, uint64_t ticket, double timeout_s);
+mvp_status mvp_ticket_release(mvp_ctx *ctx, uint64_t ticket);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MVP_H */

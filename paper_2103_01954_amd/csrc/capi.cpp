@@ -1,0 +1,474 @@
+// C ABI of libmvp: contexts, the per-frame acceleration structure, forward and
+// backward marches, and the test exports.  Serving lives in serve.cpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "ctx.h"
+
+namespace mvp {
+
+static thread_local std::string g_error = "no error";
+
+void set_error(const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+}
+
+mvp_status status_of(hipError_t e) {
+  if (e == hipSuccess) return MVP_OK;
+  return e == hipErrorOutOfMemory ? MVP_ERR_OOM : MVP_ERR_DEVICE;
+}
+
+#define MVP_HIP(expr)                                                      \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess) {                                                \
+      set_error("%s failed: %s", #expr, hipGetErrorString(e_));           \
+      return status_of(e_);                                                \
+    }                                                                      \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// arena
+// ---------------------------------------------------------------------------
+
+static size_t round_size(size_t b) {
+  if (b < 256) b = 256;
+  const size_t q = b < (1u << 20) ? 256 : (2u << 20);
+  return (b + q - 1) / q * q;
+}
+
+Arena::~Arena() {
+  std::lock_guard<std::mutex> g(mu_);
+  for (auto &p : pending_) {
+    (void)hipEventSynchronize(p.ev);
+    (void)hipEventDestroy(p.ev);
+    for (void *b : p.blocks) free_.emplace(size_[b], b);
+  }
+  pending_.clear();
+  trim_locked();
+  for (auto &kv : size_) (void)hipFree(kv.first);   // blocks still owned by live objects
+}
+
+void Arena::reap_locked() {
+  for (size_t i = 0; i < pending_.size();) {
+    if (hipEventQuery(pending_[i].ev) == hipSuccess) {
+      (void)hipEventDestroy(pending_[i].ev);
+      for (void *b : pending_[i].blocks) free_.emplace(size_[b], b);
+      pending_[i] = pending_.back();
+      pending_.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+
+void Arena::trim_locked() {
+  for (auto &kv : free_) {
+    (void)hipFree(kv.second);
+    held_ -= kv.first;
+    size_.erase(kv.second);
+  }
+  free_.clear();
+}
+
+void Arena::trim() {
+  std::lock_guard<std::mutex> g(mu_);
+  reap_locked();
+  trim_locked();
+}
+
+size_t Arena::held_bytes() {
+  std::lock_guard<std::mutex> g(mu_);
+  return held_;
+}
+
+mvp_status Arena::alloc(size_t bytes, void **out) {
+  const size_t sz = round_size(bytes);
+  std::lock_guard<std::mutex> g(mu_);
+  reap_locked();
+  auto it = free_.lower_bound(sz);
+  if (it != free_.end() && it->first <= 2 * sz) {
+    *out = it->second;
+    free_.erase(it);
+    return MVP_OK;
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, sz);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    trim_locked();
+    e = hipMalloc(&p, sz);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation of %zu bytes failed: %s", sz, hipGetErrorString(e));
+    return status_of(e);
+  }
+  size_[p] = sz;
+  held_ += sz;
+  *out = p;
+  return MVP_OK;
+}
+
+void Arena::release_now(void *p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(mu_);
+  free_.emplace(size_[p], p);
+}
+
+mvp_status Arena::release_after(const std::vector<void *> &blocks, hipStream_t s) {
+  if (blocks.empty()) return MVP_OK;
+  hipEvent_t ev;
+  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev, s);
+  std::lock_guard<std::mutex> g(mu_);
+  if (e != hipSuccess) {
+    // cannot track completion: wait for the stream instead
+    (void)hipStreamSynchronize(s);
+    for (void *b : blocks) free_.emplace(size_[b], b);
+    set_error("event record failed: %s", hipGetErrorString(e));
+    return MVP_ERR_DEVICE;
+  }
+  pending_.push_back({ev, blocks});
+  return MVP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// argument checks
+// ---------------------------------------------------------------------------
+
+mvp_status check_prims(const mvp_prims *p, bool need_payload) {
+  if (!p) { set_error("prims is NULL"); return MVP_ERR_INVALID; }
+  if (p->n_prim < 0) { set_error("n_prim < 0"); return MVP_ERR_INVALID; }
+  if (p->M < 2 || p->M > 1024) { set_error("payload size M=%d out of range [2,1024]", p->M); return MVP_ERR_INVALID; }
+  if (p->payload_dtype != MVP_F32 && p->payload_dtype != MVP_BF16) { set_error("bad payload dtype"); return MVP_ERR_INVALID; }
+  if ((int64_t)p->M * p->M * p->M * (int64_t)p->n_prim > (int64_t)1 << 40) { set_error("payload too large"); return MVP_ERR_INVALID; }
+  if ((int64_t)p->M * p->M * p->M >= (int64_t)1 << 31) { set_error("M^3 too large"); return MVP_ERR_INVALID; }
+  if (p->n_prim > 0) {
+    if (!p->pos || !p->rot || !p->scale) { set_error("pos/rot/scale pointer is NULL"); return MVP_ERR_INVALID; }
+    if (need_payload && !p->payload) { set_error("payload pointer is NULL"); return MVP_ERR_INVALID; }
+    const size_t align = p->payload_dtype == MVP_F32 ? 16 : 8;
+    if (need_payload && ((uintptr_t)p->payload % align)) { set_error("payload not %zu-byte aligned", align); return MVP_ERR_INVALID; }
+  }
+  return MVP_OK;
+}
+
+mvp_status check_camera(const mvp_camera *c) {
+  if (c->width <= 0 || c->height <= 0 || c->width > 32768 || c->height > 32768) {
+    set_error("camera size %dx%d out of range", c->width, c->height);
+    return MVP_ERR_INVALID;
+  }
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(c->origin[i])) { set_error("camera origin not finite"); return MVP_ERR_INVALID; }
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(c->pix2dir[i])) { set_error("camera matrix not finite"); return MVP_ERR_INVALID; }
+  return MVP_OK;
+}
+
+mvp_status check_params(const mvp_march_params *p) {
+  if (!p) { set_error("params is NULL"); return MVP_ERR_INVALID; }
+  if (!(p->step > 0.0f) || !std::isfinite(p->step)) { set_error("step must be finite and > 0"); return MVP_ERR_INVALID; }
+  if (!(p->eps_early >= 0.0f && p->eps_early < 1.0f)) { set_error("eps_early must be in [0,1)"); return MVP_ERR_INVALID; }
+  if (!(p->t_near >= 0.0f) || !std::isfinite(p->t_near)) { set_error("t_near must be finite and >= 0"); return MVP_ERR_INVALID; }
+  return MVP_OK;
+}
+
+static bool invert3(const float *m, float *out) {
+  const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5], g = m[6], h = m[7], i = m[8];
+  const double A = e * i - f * h, B = -(d * i - f * g), C = d * h - e * g;
+  const double det = a * A + b * B + c * C;
+  if (!(std::fabs(det) > 0) || !std::isfinite(det)) return false;
+  const double inv[9] = {A, -(b * i - c * h), b * f - c * e, B, a * i - c * g, -(a * f - c * d),
+                         C, -(a * h - b * g), a * e - b * d};
+  for (int k = 0; k < 9; ++k) out[k] = (float)(inv[k] / det);
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// acceleration structure
+// ---------------------------------------------------------------------------
+
+namespace {
+// Device blocks of one call; on an error path they are recycled once the work
+// already enqueued on the stream has finished.
+struct Blocks {
+  mvp_ctx *ctx;
+  hipStream_t s;
+  std::vector<void *> list;
+  bool keep = false;
+  template <typename T>
+  mvp_status get(T **p, size_t count) {
+    void *v = nullptr;
+    mvp_status st = ctx->arena.alloc(count * sizeof(T) + 16, &v);
+    if (st != MVP_OK) return st;
+    list.push_back(v);
+    *p = (T *)v;
+    return MVP_OK;
+  }
+  ~Blocks() {
+    if (!keep) ctx->arena.release_after(list, s);
+  }
+};
+}  // namespace
+
+#define MVP_CHECK(expr)                 \
+  do {                                  \
+    mvp_status st_ = (expr);            \
+    if (st_ != MVP_OK) return st_;      \
+  } while (0)
+
+static mvp_status read_u64(const uint64_t *dev, uint64_t *host, hipStream_t s) {
+  MVP_HIP(hipMemcpyAsync(host, dev, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  MVP_HIP(hipStreamSynchronize(s));
+  return MVP_OK;
+}
+
+mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams, int32_t n_views,
+                       const mvp_march_params *params, mvp_accel **out, hipStream_t s, const Admit *admit) {
+  if (!ctx || !out || !cams) { set_error("NULL argument"); return MVP_ERR_INVALID; }
+  *out = nullptr;
+  MVP_CHECK(check_prims(prims, false));
+  MVP_CHECK(check_params(params));
+  if (n_views < 1) { set_error("n_views must be >= 1"); return MVP_ERR_INVALID; }
+  for (int v = 0; v < n_views; ++v) {
+    MVP_CHECK(check_camera(&cams[v]));
+    if (cams[v].width != cams[0].width || cams[v].height != cams[0].height) {
+      set_error("all views of one structure must share a resolution");
+      return MVP_ERR_INVALID;
+    }
+  }
+  const int W = cams[0].width, H = cams[0].height, N = prims->n_prim;
+  const int tx = (W + kTile - 1) / kTile, ty = (H + kTile - 1) / kTile;
+  const size_t ntile = (size_t)n_views * tx * ty;
+  const size_t R = (size_t)n_views * W * H;
+  if (ntile >= (size_t)1 << 31) { set_error("too many tiles"); return MVP_ERR_INVALID; }
+
+  mvp_accel *a = new (std::nothrow) mvp_accel();
+  if (!a) { set_error("host allocation failed"); return MVP_ERR_OOM; }
+  a->ctx = ctx; a->V = n_views; a->W = W; a->H = H; a->N = N; a->tiles_x = tx; a->tiles_y = ty;
+  a->params = *params;
+  a->cams_host.resize(n_views);
+  for (int v = 0; v < n_views; ++v) {
+    DevCam &c = a->cams_host[v];
+    memcpy(c.o, cams[v].origin, sizeof c.o);
+    memcpy(c.P, cams[v].pix2dir, sizeof c.P);
+    c.W = W;
+    c.H = H;
+    if (!invert3(c.P, c.Pinv)) {
+      delete a;
+      set_error("camera matrix of view %d is singular", v);
+      return MVP_ERR_INVALID;
+    }
+  }
+  struct Guard {
+    mvp_accel *a;
+    bool keep = false;
+    ~Guard() { if (!keep) delete a; }
+  } guard{a};
+
+  MVP_HIP(hipSetDevice(ctx->device));
+  Blocks keep{ctx, s}, temp{ctx, s};
+  int4 *rect = nullptr;
+  uint32_t *tile_cnt = nullptr, *ray_cnt = nullptr;
+  void *scratch = nullptr;
+  const size_t sb = scan_scratch_bytes(ntile > R ? ntile : R);
+  if (admit) {
+    const size_t base = n_views * sizeof(DevCam) + 3 * (size_t)N * 16 + (ntile + 1) * 8 + (R + 1) * 8 + 16 +
+                        (size_t)n_views * N * 16 + ntile * 4 + R * 4 + sb + 9 * 256;
+    MVP_CHECK(admit->fn(admit->user, base));
+  }
+  MVP_CHECK(keep.get(&a->cams, n_views));
+  MVP_CHECK(keep.get(&a->xf, 3 * (size_t)N));
+  MVP_CHECK(keep.get(&a->tile_off, ntile + 1));
+  MVP_CHECK(keep.get(&a->ray_off, R + 1));
+  MVP_CHECK(keep.get(&a->counters, 2));
+  MVP_CHECK(temp.get(&rect, (size_t)n_views * N));
+  MVP_CHECK(temp.get(&tile_cnt, ntile));
+  MVP_CHECK(temp.get(&ray_cnt, R));
+  {
+    uint8_t *sp = nullptr;
+    MVP_CHECK(temp.get(&sp, sb));
+    scratch = sp;
+  }
+  MVP_HIP(hipMemcpyAsync(a->cams, a->cams_host.data(), n_views * sizeof(DevCam), hipMemcpyHostToDevice, s));
+  AccelView av = a->view(2);
+
+  // culling lists
+  MVP_HIP(launch_zero_u32(tile_cnt, ntile, s));
+  MVP_HIP(launch_prep(*prims, av, a->xf, rect, tile_cnt, s));
+  MVP_HIP(launch_scan_u32_u64(tile_cnt, a->tile_off, ntile, scratch, s));
+  uint64_t n_tile_pairs = 0;
+  MVP_CHECK(read_u64(a->tile_off + ntile, &n_tile_pairs, s));
+  if (admit) MVP_CHECK(admit->fn(admit->user, n_tile_pairs * 4 + 256));
+  MVP_CHECK(keep.get(&a->tile_list, n_tile_pairs ? n_tile_pairs : 1));
+  av = a->view(2);
+  MVP_HIP(launch_zero_u32(tile_cnt, ntile, s));
+  MVP_HIP(launch_tile_fill(av, rect, tile_cnt, a->tile_list, s));
+
+  // per-ray pair lists
+  MVP_HIP(launch_hit_count(av, 0, ray_cnt, s));
+  MVP_HIP(launch_scan_u32_u64(ray_cnt, a->ray_off, R, scratch, s));
+  uint64_t n_pairs = 0;
+  MVP_CHECK(read_u64(a->ray_off + R, &n_pairs, s));
+  if (admit) MVP_CHECK(admit->fn(admit->user, n_pairs * 36 + 3 * 256));
+  MVP_CHECK(keep.get(&a->pa, n_pairs ? n_pairs : 1));
+  MVP_CHECK(keep.get(&a->pb, n_pairs ? n_pairs : 1));
+  MVP_CHECK(keep.get(&a->pid, n_pairs ? n_pairs : 1));
+  av = a->view(2);
+  MVP_HIP(launch_hit_emit(av, 0, a->pa, a->pb, a->pid, s));
+
+  a->n_tile_pairs = (int64_t)n_tile_pairs;
+  a->n_ray_pairs = (int64_t)n_pairs;
+  a->bytes = (int64_t)(n_views * sizeof(DevCam) + 3 * (size_t)N * 16 + (ntile + 1) * 8 + (R + 1) * 8 +
+                       n_tile_pairs * 4 + n_pairs * 36);
+  a->blocks = keep.list;
+  keep.keep = true;
+  // temporaries are recycled once the emit kernel has run
+  MVP_CHECK(ctx->arena.release_after(temp.list, s));
+  temp.keep = true;
+  guard.keep = true;
+  ctx->live_accels.fetch_add(1);
+  *out = a;
+  return MVP_OK;
+}
+
+mvp_status destroy_accel(mvp_ctx *ctx, mvp_accel *a, hipStream_t s) {
+  if (!ctx || !a || a->ctx != ctx) { set_error("bad accel handle"); return MVP_ERR_INVALID; }
+  mvp_status st = ctx->arena.release_after(a->blocks, s);
+  ctx->live_accels.fetch_sub(1);
+  delete a;
+  return st;
+}
+
+static mvp_status check_render(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *p) {
+  if (!ctx || !a || a->ctx != ctx) { set_error("bad context or accel handle"); return MVP_ERR_INVALID; }
+  MVP_CHECK(check_prims(p, true));
+  if (p->n_prim != a->N) { set_error("prims has %d primitives, accel was built for %d", p->n_prim, a->N); return MVP_ERR_INVALID; }
+  return MVP_OK;
+}
+
+}  // namespace mvp
+
+using namespace mvp;
+
+// ---------------------------------------------------------------------------
+// exported C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *mvp_last_error(void) { return g_error.c_str(); }
+const char *mvp_version(void) { return "mvp-mi355x 0.1 (gfx950)"; }
+
+mvp_status mvp_create(int device, mvp_ctx **out) {
+  if (!out) { set_error("out is NULL"); return MVP_ERR_INVALID; }
+  *out = nullptr;
+  int n = 0;
+  MVP_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) { set_error("device %d out of range (%d devices)", device, n); return MVP_ERR_INVALID; }
+  MVP_HIP(hipSetDevice(device));
+  mvp_ctx *c = new (std::nothrow) mvp_ctx(device);
+  if (!c) { set_error("host allocation failed"); return MVP_ERR_OOM; }
+  *out = c;
+  return MVP_OK;
+}
+
+mvp_status mvp_destroy(mvp_ctx *ctx) {
+  if (!ctx) { set_error("ctx is NULL"); return MVP_ERR_INVALID; }
+  if (ctx->live_accels.load() != 0) { set_error("%d acceleration structures still alive", ctx->live_accels.load()); return MVP_ERR_BUSY; }
+  serve_shutdown(ctx);
+  (void)hipSetDevice(ctx->device);
+  delete ctx;
+  return MVP_OK;
+}
+
+mvp_status mvp_build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams, int32_t n_views,
+                           const mvp_march_params *params, mvp_accel **out, void *stream) {
+  return build_accel(ctx, prims, cams, n_views, params, out, (hipStream_t)stream, nullptr);
+}
+
+mvp_status mvp_accel_destroy(mvp_ctx *ctx, mvp_accel *accel, void *stream) {
+  return destroy_accel(ctx, accel, (hipStream_t)stream);
+}
+
+mvp_status mvp_accel_get_info(const mvp_accel *a, mvp_accel_info *info) {
+  if (!a || !info) { set_error("NULL argument"); return MVP_ERR_INVALID; }
+  info->n_views = a->V; info->width = a->W; info->height = a->H; info->n_prim = a->N;
+  info->n_tile_pairs = a->n_tile_pairs; info->n_ray_pairs = a->n_ray_pairs; info->device_bytes = a->bytes;
+  return MVP_OK;
+}
+
+mvp_status mvp_render_fwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims, float *rgba,
+                          mvp_ray_aux *aux, void *stream) {
+  MVP_CHECK(check_render(ctx, a, prims));
+  if (!rgba) { set_error("rgba is NULL"); return MVP_ERR_INVALID; }
+  hipStream_t s = (hipStream_t)stream;
+  MVP_HIP(hipSetDevice(ctx->device));
+  MVP_HIP(launch_zero_u64((uint64_t *)a->counters, 2, s));
+  MVP_HIP(launch_march_fwd(a->view(prims->M), *prims, rgba, aux, a->counters, s));
+  return MVP_OK;
+}
+
+mvp_status mvp_render_bwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims, const mvp_ray_aux *aux,
+                          const float *grad_rgba, float *grad_payload, float *grad_pos, float *grad_rot,
+                          float *grad_scale, void *stream) {
+  MVP_CHECK(check_render(ctx, a, prims));
+  if (!aux || !grad_rgba) { set_error("aux and grad_rgba are required"); return MVP_ERR_INVALID; }
+  hipStream_t s = (hipStream_t)stream;
+  MVP_HIP(hipSetDevice(ctx->device));
+  MVP_HIP(launch_march_bwd(a->view(prims->M), *prims, aux, grad_rgba, grad_payload, grad_pos, grad_rot,
+                           grad_scale, s));
+  return MVP_OK;
+}
+
+mvp_status mvp_accel_counts(mvp_ctx *ctx, const mvp_accel *a, uint64_t *ray_samples, uint64_t *prim_samples,
+                            void *stream) {
+  if (!ctx || !a || a->ctx != ctx || !ray_samples || !prim_samples) { set_error("bad argument"); return MVP_ERR_INVALID; }
+  hipStream_t s = (hipStream_t)stream;
+  MVP_HIP(hipSetDevice(ctx->device));
+  uint64_t h[2] = {0, 0};
+  MVP_HIP(hipMemcpyAsync(h, a->counters, sizeof h, hipMemcpyDeviceToHost, s));
+  MVP_HIP(hipStreamSynchronize(s));
+  *ray_samples = h[0];
+  *prim_samples = h[1];
+  return MVP_OK;
+}
+
+mvp_status mvp_debug_hits(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims, int64_t *offsets,
+                          int32_t *ids, int64_t ids_cap, int64_t *n_total, void *stream) {
+  if (!ctx || !a || a->ctx != ctx || !offsets || !n_total || ids_cap < 0) { set_error("bad argument"); return MVP_ERR_INVALID; }
+  MVP_CHECK(check_prims(prims, false));
+  if (prims->n_prim != a->N) { set_error("prims does not match the accel"); return MVP_ERR_INVALID; }
+  hipStream_t s = (hipStream_t)stream;
+  MVP_HIP(hipSetDevice(ctx->device));
+  const size_t R = a->n_rays();
+  Blocks temp{ctx, s};
+  uint32_t *cnt = nullptr;
+  uint8_t *scratch = nullptr;
+  MVP_CHECK(temp.get(&cnt, R));
+  MVP_CHECK(temp.get(&scratch, scan_scratch_bytes(R)));
+  AccelView av = a->view(prims->M);
+  MVP_HIP(launch_hit_count(av, 1, cnt, s));
+  MVP_HIP(launch_scan_u32_u64(cnt, (uint64_t *)offsets, R, scratch, s));
+  uint64_t total = 0;
+  MVP_CHECK(read_u64((const uint64_t *)offsets + R, &total, s));
+  *n_total = (int64_t)total;
+  if ((int64_t)total > ids_cap) { set_error("ids_cap %lld < %llu hits", (long long)ids_cap, (unsigned long long)total); return MVP_ERR_OOM; }
+  if (total > 0 && !ids) { set_error("ids is NULL"); return MVP_ERR_INVALID; }
+  av.ray_off = (const uint64_t *)offsets;
+  MVP_HIP(launch_hit_emit(av, 1, nullptr, nullptr, ids, s));
+  MVP_HIP(hipStreamSynchronize(s));
+  return MVP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Host-side runtime objects behind the C ABI: error state, the caching device
+// memory arena, contexts and acceleration structures.
+#pragma once
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+namespace mvp {
+
+// Record a message for mvp_last_error() on this thread.
+void set_error(const char *fmt, ...);
+mvp_status status_of(hipError_t e);
+
+// Caching allocator for library-owned device memory.  Blocks released with a
+// stream go back to the cache only after the work enqueued on that stream has
+// finished (an event is recorded at release time), so memory can be recycled
+// across frames without synchronising the device.
+class Arena {
+ public:
+  explicit Arena(int device) : device_(device) {}
+  ~Arena();
+  mvp_status alloc(size_t bytes, void **out);
+  // recycle after the work already enqueued on `s` completes
+  mvp_status release_after(const std::vector<void *> &blocks, hipStream_t s);
+  void release_now(void *p);
+  size_t held_bytes();
+  void trim();
+
+ private:
+  struct Pending {
+    hipEvent_t ev;
+    std::vector<void *> blocks;
+  };
+  void reap_locked();
+  void trim_locked();
+  int device_;
+  std::mutex mu_;
+  std::multimap<size_t, void *> free_;
+  std::unordered_map<void *, size_t> size_;
+  std::vector<Pending> pending_;
+  size_t held_ = 0;
+};
+
+class Server;  // serving scheduler (serve.cpp)
+
+}  // namespace mvp
+
+struct mvp_ctx {
+  int device = 0;
+  mvp::Arena arena;
+  std::atomic<int> live_accels{0};
+  mvp::Server *server = nullptr;
+  explicit mvp_ctx(int dev) : device(dev), arena(dev) {}
+};
+
+struct mvp_accel {
+  mvp_ctx *ctx = nullptr;
+  int32_t V = 0, W = 0, H = 0, N = 0, tiles_x = 0, tiles_y = 0;
+  mvp_march_params params{};
+  std::vector<mvp::DevCam> cams_host;
+  mvp::DevCam *cams = nullptr;
+  float4 *xf = nullptr;
+  uint64_t *tile_off = nullptr;
+  uint32_t *tile_list = nullptr;
+  uint64_t *ray_off = nullptr;
+  float4 *pa = nullptr, *pb = nullptr;
+  int32_t *pid = nullptr;
+  unsigned long long *counters = nullptr;
+  int64_t n_tile_pairs = 0, n_ray_pairs = 0, bytes = 0;
+  std::vector<void *> blocks;
+
+  mvp::AccelView view(int M) const {
+    mvp::AccelView v{};
+    v.V = V; v.W = W; v.H = H; v.N = N; v.M = M;
+    v.tiles_x = tiles_x; v.tiles_y = tiles_y;
+    v.step = params.step; v.eps = params.eps_early; v.t_near = params.t_near;
+    v.cams = cams; v.xf = xf; v.tile_off = tile_off; v.tile_list = tile_list;
+    v.ray_off = ray_off; v.pa = pa; v.pb = pb; v.pid = pid;
+    return v;
+  }
+  size_t n_rays() const { return (size_t)V * H * W; }
+};
+
+namespace mvp {
+// Build / check helpers shared with the serving scheduler.
+mvp_status check_prims(const mvp_prims *p, bool need_payload);
+mvp_status check_camera(const mvp_camera *c);
+mvp_status check_params(const mvp_march_params *p);
+// Optional admission hook: called before each group of device allocations of a
+// build with the number of bytes about to be allocated; a non-OK status aborts
+// the build.
+struct Admit {
+  mvp_status (*fn)(void *user, size_t bytes);
+  void *user;
+};
+mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams, int32_t n_views,
+                       const mvp_march_params *params, mvp_accel **out, hipStream_t s, const Admit *admit);
+mvp_status destroy_accel(mvp_ctx *ctx, mvp_accel *a, hipStream_t s);
+// stop the serving scheduler of a context (waits for its work)
+void serve_shutdown(mvp_ctx *ctx);
+}  // namespace mvp

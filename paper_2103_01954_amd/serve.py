@@ -1,0 +1,139 @@
+"""Client of the library's serving scheduler (mvp_serve_configure / mvp_scene_create /
+mvp_submit / mvp_poll): resident scenes, continuous batching, latency stats.
+
+The scheduling itself (admission by memory, slot streams, completion stamps)
+runs in the library's host C++ thread; this module only submits requests and
+reads their tickets.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import time
+from dataclasses import dataclass
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import scenes
+from .api import Context, DevicePrims, c_camera, c_params
+
+STATE = {0: "queued", 1: "running", 2: "done", 3: "failed"}
+
+
+class Server:
+    def __init__(self, ctx: Context, budget_bytes: int = 32 << 30, slots: int = 4):
+        self.ctx = ctx
+        st = ctx.lib.mvp_serve_configure(ctx.handle, int(budget_bytes), int(slots))
+        if st == L.MVP_ERR_BUSY:
+            pass   # already configured on this context
+        else:
+            L.check("mvp_serve_configure", st)
+
+    def add_scene(self, prims: DevicePrims) -> int:
+        cp = prims.c_struct()
+        sid = C.c_uint64()
+        L.check("mvp_scene_create", self.ctx.lib.mvp_scene_create(self.ctx.handle, C.byref(cp), C.byref(sid)))
+        return sid.value
+
+    def release_scene(self, sid: int) -> int:
+        return self.ctx.lib.mvp_scene_release(self.ctx.handle, C.c_uint64(sid))
+
+    def submit(self, sid: int, cam: scenes.Camera, params: scenes.MarchParams, out: torch.Tensor) -> int:
+        assert out.is_contiguous() and out.dtype == torch.float32
+        assert out.numel() >= cam.width * cam.height * 4
+        req = L.mvp_request(sid, c_camera(cam), c_params(params), out.data_ptr())
+        t = C.c_uint64()
+        L.check("mvp_submit", self.ctx.lib.mvp_submit(self.ctx.handle, C.byref(req), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        s, a, b = C.c_int32(), C.c_double(), C.c_double()
+        L.check("mvp_poll", self.ctx.lib.mvp_poll(self.ctx.handle, C.c_uint64(ticket), C.byref(s), C.byref(a),
+                                                  C.byref(b)))
+        return s.value, a.value, b.value
+
+    def wait(self, ticket: int, timeout_s: float = 60.0) -> int:
+        return self.ctx.lib.mvp_wait(self.ctx.handle, C.c_uint64(ticket), float(timeout_s))
+
+    def release(self, ticket: int):
+        L.check("mvp_ticket_release", self.ctx.lib.mvp_ticket_release(self.ctx.handle, C.c_uint64(ticket)))
+
+
+@dataclass
+class Result:
+    latency_ms: List[float]
+    wall_s: float
+    n: int
+    failed: int
+
+
+def _run(srv: Server, sids, reqs, params, arrivals: Optional[np.ndarray], bufs) -> Result:
+    """Submit requests at the given arrival offsets (None: all at once) and wait
+    for all of them.  bufs: one output buffer per request slot in use."""
+    n = len(reqs)
+    pending = {}
+    lat = []
+    failed = 0
+    t0 = time.perf_counter()
+    i = 0
+    free = list(range(len(bufs)))
+    while i < n or pending:
+        now = time.perf_counter() - t0
+        while i < n and free and (arrivals is None or arrivals[i] <= now):
+            si, cam = reqs[i]
+            b = free.pop()
+            t = srv.submit(sids[si], cam, params, bufs[b])
+            pending[t] = b
+            i += 1
+        for t in list(pending):
+            s, ts, td = srv.poll(t)
+            if s >= 2:
+                if s == 2:
+                    lat.append((td - ts) * 1e3)
+                else:
+                    failed += 1
+                free.append(pending.pop(t))
+                srv.release(t)
+        time.sleep(0.0002)
+    return Result(lat, time.perf_counter() - t0, n, failed)
+
+
+def poisson_benchmark(ctx: Context, n_requests: int = 120, seed: int = 5, n_scenes: int = 6,
+                      load: float = 0.8, budget_bytes: int = 32 << 30, slots: int = 4) -> dict:
+    """Resident BF16 scenes of 256..16384 primitives and 8^3..16^3 payloads;
+    requests at 256^2..1920x1080.  Measures closed-loop capacity, then an open
+    Poisson stream at `load` x capacity; reports p50/p99 latency."""
+    srv = Server(ctx, budget_bytes, slots)
+    specs = scenes.serving_scene_specs(seed=4, count=16)[:n_scenes]
+    sids = []
+    for spec in specs:
+        dp = DevicePrims.from_host(scenes.serving_scene(spec), bf16=True)
+        sids.append(srv.add_scene(dp))
+        del dp
+    params = scenes.MarchParams(1.0 / 512, 1e-6)
+    reqs = scenes.serving_requests(seed, n_requests, len(sids))
+    maxpix = max(w * h for w, h in scenes.SERVE_RESOLUTIONS)
+    bufs = [torch.empty(maxpix * 4, dtype=torch.float32, device="cuda") for _ in range(16)]
+    torch.cuda.synchronize()
+    warm = _run(srv, sids, reqs[: min(8, n_requests)], params, None, bufs)
+    closed = _run(srv, sids, reqs, params, None, bufs)
+    capacity = closed.n / closed.wall_s
+    rate = load * capacity
+    gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, size=n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    opened = _run(srv, sids, reqs, params, arrivals, bufs)
+    for s in sids:
+        srv.release_scene(s)
+    lat = np.array(opened.latency_ms)
+    return {
+        "scenes": [{"n": s[0], "m": s[1]} for s in specs],
+        "requests": n_requests, "slots": slots, "budget_gib": budget_bytes / 2 ** 30,
+        "capacity_fps": round(capacity, 1), "load": load, "offered_fps": round(rate, 1),
+        "achieved_fps": round(opened.n / opened.wall_s, 1),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3) if lat.size else None,
+        "p99_ms": round(float(np.percentile(lat, 99)), 3) if lat.size else None,
+        "closed_loop_p50_ms": round(float(np.percentile(closed.latency_ms, 50)), 3) if closed.latency_ms else None,
+        "failed": opened.failed + closed.failed + warm.failed,
+    }
