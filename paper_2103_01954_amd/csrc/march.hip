@@ -23,6 +23,7 @@
 //
 // Built with -ffp-contract=off; fused multiply-adds are written explicitly.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 
 #include "internal.h"
 
@@ -132,7 +133,168 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // forward
 // ---------------------------------------------------------------------------
 
+// Trilinear RGBA from the 8 cached corners of a cell (corner q = dx + 2 dy + 4 dz).
+__device__ __forceinline__ float4 trilerp(const float4 (&v)[8], const Cell &c) {
+  const float4 c00 = lerp4(v[0], v[1], c.f[0]);
+  const float4 c10 = lerp4(v[2], v[3], c.f[0]);
+  const float4 c01 = lerp4(v[4], v[5], c.f[0]);
+  const float4 c11 = lerp4(v[6], v[7], c.f[0]);
+  const float4 c0 = lerp4(c00, c10, c.f[1]);
+  const float4 c1 = lerp4(c01, c11, c.f[1]);
+  return lerp4(c0, c1, c.f[2]);
+}
+
 template <bool BF16>
+__device__ __forceinline__ void load_corners(const void *pay, size_t b0, int M, float4 (&v)[8]) {
+  const size_t MM = (size_t)M * M;
+  v[0] = Voxels<BF16>::load(pay, b0);
+  v[1] = Voxels<BF16>::load(pay, b0 + 1);
+  v[2] = Voxels<BF16>::load(pay, b0 + M);
+  v[3] = Voxels<BF16>::load(pay, b0 + M + 1);
+  v[4] = Voxels<BF16>::load(pay, b0 + MM);
+  v[5] = Voxels<BF16>::load(pay, b0 + MM + 1);
+  v[6] = Voxels<BF16>::load(pay, b0 + MM + M);
+  v[7] = Voxels<BF16>::load(pay, b0 + MM + M + 1);
+}
+
+// Accumulated state of one ray.
+struct RayState {
+  float T = 0.f, I0 = 0.f, I1 = 0.f, I2 = 0.f, t_prev = -1.0f;
+  int j_end = -1;
+  unsigned long long n_ray = 0, n_prim = 0;
+};
+
+// One clamped additive step with the summed density sig and summed
+// density-weighted colour (c0,c1,c2) of sample j.  Returns true to stop.
+__device__ __forceinline__ bool composite(RayState &st, int j, float sig, float c0, float c1, float c2,
+                                          float dt, float lim) {
+  st.j_end = j;
+  const float Tn = st.T + sig * dt;
+  if (Tn <= 1.0f) {
+    st.T = Tn;
+    st.I0 = fmaf(c0, dt, st.I0);
+    st.I1 = fmaf(c1, dt, st.I1);
+    st.I2 = fmaf(c2, dt, st.I2);
+    return st.T > lim;
+  }
+  const float w = (1.0f - st.T) / sig;
+  st.I0 = fmaf(c0, w, st.I0);
+  st.I1 = fmaf(c1, w, st.I1);
+  st.I2 = fmaf(c2, w, st.I2);
+  st.t_prev = st.T;
+  st.T = 1.0f;
+  return true;
+}
+
+// Sample by sample: at each sample, every open pair of the ray is evaluated.
+template <bool BF16>
+__device__ void march_ray_samples(const AccelView &av, const void *pay, uint64_t beg, uint64_t end, RayState &st) {
+  const float dt = av.step, lim = 1.0f - av.eps;
+  const int M = av.M;
+  const float hM = 0.5f * (float)(M - 1);
+  const size_t M3 = (size_t)M * M * M;
+  uint64_t base = beg, nxt = beg;
+  int j = jlo_of(av.pa[beg]);
+  while (true) {
+    // open every pair whose interval has started; drop finished ones in front
+    while (nxt < end && jlo_of(av.pa[nxt]) <= j) ++nxt;
+    while (base < nxt && jhi_of(av.pb[base]) < j) ++base;
+    if (base == nxt) {
+      if (nxt == end) break;
+      j = jlo_of(av.pa[nxt]);   // skip empty space to the next pair
+      continue;
+    }
+    const float tau = (float)j * dt;
+    float sig = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    for (uint64_t e = base; e < nxt; ++e) {
+      const float4 B = av.pb[e];
+      if (jhi_of(B) < j) continue;
+      const float4 A = av.pa[e];
+      const Cell c = locate(A, B, tau, M, hM);
+      const float4 s = trilinear<BF16>(pay, (size_t)av.pid[e] * M3 + c.idx, M, c);
+      sig += s.w;
+      c0 = fmaf(s.w, s.x, c0);
+      c1 = fmaf(s.w, s.y, c1);
+      c2 = fmaf(s.w, s.z, c2);
+      ++st.n_prim;
+    }
+    ++st.n_ray;
+    if (composite(st, j, sig, c0, c1, c2, dt, lim)) break;
+    ++j;
+  }
+}
+
+// Window by window: the samples J..J+kWin-1 of a ray are gathered pair by pair
+// into per-sample sums held in registers (the voxel corners of a pair stay in
+// registers while consecutive samples remain in one cell), then composited in
+// sample order.  Same sums in the same order as sample by sample.
+constexpr int kWin = 8;
+
+template <bool BF16>
+__device__ void march_ray_windows(const AccelView &av, const void *pay, uint64_t beg, uint64_t end, RayState &st) {
+  const float dt = av.step, lim = 1.0f - av.eps;
+  const int M = av.M;
+  const float hM = 0.5f * (float)(M - 1);
+  const size_t M3 = (size_t)M * M * M;
+  uint64_t e0 = beg;
+  int J = jlo_of(av.pa[beg]);
+  while (true) {
+    float as[kWin], ar[kWin], ag[kWin], ab[kWin];
+    int cnt[kWin];
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) {
+      as[w] = ar[w] = ag[w] = ab[w] = 0.f;
+      cnt[w] = 0;
+    }
+    for (uint64_t e = e0; e < end; ++e) {
+      const float4 A = av.pa[e];
+      const int jl = jlo_of(A);
+      if (jl >= J + kWin) break;
+      const float4 B = av.pb[e];
+      const int jh = jhi_of(B);
+      if (jh < J) continue;
+      const int lo = max(jl, J) - J, hi = min(jh, J + kWin - 1) - J;
+      const size_t kb = (size_t)av.pid[e] * M3;
+      int cur = -1;
+      float4 v[8];
+#pragma unroll
+      for (int w = 0; w < kWin; ++w) {
+        if (w >= lo && w <= hi) {
+          const float tau = (float)(J + w) * dt;
+          const Cell c = locate(A, B, tau, M, hM);
+          if (c.idx != cur) {
+            load_corners<BF16>(pay, kb + c.idx, M, v);
+            cur = c.idx;
+          }
+          const float4 s = trilerp(v, c);
+          as[w] += s.w;
+          ar[w] = fmaf(s.w, s.x, ar[w]);
+          ag[w] = fmaf(s.w, s.y, ag[w]);
+          ab[w] = fmaf(s.w, s.z, ab[w]);
+          ++cnt[w];
+        }
+      }
+    }
+    bool stop = false;
+#pragma unroll
+    for (int w = 0; w < kWin; ++w) {
+      if (!stop && cnt[w] > 0) {
+        ++st.n_ray;
+        st.n_prim += cnt[w];
+        stop = composite(st, J + w, as[w], ar[w], ag[w], ab[w], dt, lim);
+      }
+    }
+    if (stop) break;
+    J += kWin;
+    // the next occupied sample: pairs in front of e0 have all ended before J,
+    // and every later pair starts no earlier than e0
+    while (e0 < end && jhi_of(av.pb[e0]) < J) ++e0;
+    if (e0 == end) break;
+    J = max(J, jlo_of(av.pa[e0]));
+  }
+}
+
+template <bool BF16, bool WINDOWS>
 __global__ __launch_bounds__(kTileThreads) void k_march_fwd(AccelView av, const void *__restrict__ pay,
                                                              float4 *__restrict__ rgba,
                                                              mvp_ray_aux *__restrict__ aux,
@@ -162,87 +324,57 @@ __global__ __launch_bounds__(kTileThreads) void k_march_fwd(AccelView av, const 
 #pragma unroll
   for (int w = 0; w < kTileThreads / kWave; ++w) total += s_wave[w];
 
-  unsigned long long n_ray = 0, n_prim = 0;
+  RayState st;
   if ((int)threadIdx.x < total) {
     const int lp = s_list[threadIdx.x];
     const int px = tx0 + (lp % kTile), py = ty0 + (lp / kTile);
     const size_t ray = ((size_t)v * av.H + py) * av.W + px;
     const uint64_t beg = av.ray_off[ray], end = av.ray_off[ray + 1];
-    const float dt = av.step, lim = 1.0f - av.eps;
-    const int M = av.M;
-    const float hM = 0.5f * (float)(M - 1);
-    const size_t M3 = (size_t)M * M * M;
-
-    float T_ = 0.f, I0 = 0.f, I1 = 0.f, I2 = 0.f, t_prev = -1.0f;
-    int j_end = -1;
-    uint64_t base = beg, nxt = beg;
-    int j = jlo_of(av.pa[beg]);
-    while (true) {
-      // open every pair whose interval has started; drop finished ones in front
-      while (nxt < end && jlo_of(av.pa[nxt]) <= j) ++nxt;
-      while (base < nxt && jhi_of(av.pb[base]) < j) ++base;
-      if (base == nxt) {
-        if (nxt == end) break;
-        j = jlo_of(av.pa[nxt]);   // skip empty space to the next entry
-        continue;
-      }
-      const float tau = (float)j * dt;
-      float sig = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-      for (uint64_t e = base; e < nxt; ++e) {
-        const float4 B = av.pb[e];
-        if (jhi_of(B) < j) continue;
-        const float4 A = av.pa[e];
-        const Cell c = locate(A, B, tau, M, hM);
-        const float4 s = trilinear<BF16>(pay, (size_t)av.pid[e] * M3 + c.idx, M, c);
-        sig += s.w;
-        c0 = fmaf(s.w, s.x, c0);
-        c1 = fmaf(s.w, s.y, c1);
-        c2 = fmaf(s.w, s.z, c2);
-        ++n_prim;
-      }
-      ++n_ray;
-      j_end = j;
-      const float Tn = T_ + sig * dt;
-      if (Tn <= 1.0f) {
-        T_ = Tn;
-        I0 = fmaf(c0, dt, I0);
-        I1 = fmaf(c1, dt, I1);
-        I2 = fmaf(c2, dt, I2);
-      } else {
-        const float w = (1.0f - T_) / sig;
-        I0 = fmaf(c0, w, I0);
-        I1 = fmaf(c1, w, I1);
-        I2 = fmaf(c2, w, I2);
-        t_prev = T_;
-        T_ = 1.0f;
-        break;
-      }
-      if (T_ > lim) break;
-      ++j;
-    }
-    rgba[ray] = make_float4(I0, I1, I2, T_);
-    if (aux) aux[ray] = mvp_ray_aux{j_end, t_prev};
+    if (WINDOWS)
+      march_ray_windows<BF16>(av, pay, beg, end, st);
+    else
+      march_ray_samples<BF16>(av, pay, beg, end, st);
+    rgba[ray] = make_float4(st.I0, st.I1, st.I2, st.T);
+    if (aux) aux[ray] = mvp_ray_aux{st.j_end, st.t_prev};
   }
   if (counters) {
-    n_ray = wave_sum_u64(n_ray);
-    n_prim = wave_sum_u64(n_prim);
-    if ((threadIdx.x & (kWave - 1)) == 0 && n_ray) {
-      atomicAdd(&counters[0], n_ray);
-      atomicAdd(&counters[1], n_prim);
+    const unsigned long long nr = wave_sum_u64(st.n_ray);
+    const unsigned long long np = wave_sum_u64(st.n_prim);
+    if ((threadIdx.x & (kWave - 1)) == 0 && nr) {
+      atomicAdd(&counters[0], nr);
+      atomicAdd(&counters[1], np);
     }
   }
+}
+
+static bool fwd_windows() {
+  static const bool w = [] {
+    const char *e = getenv("MVP_FWD_IMPL");
+    return !(e && e[0] == 's');
+  }();
+  return w;
 }
 
 hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, float *rgba, mvp_ray_aux *aux,
                             unsigned long long *counters, hipStream_t s) {
   const int ntile = av.V * av.tiles_x * av.tiles_y;
   if (ntile == 0) return hipSuccess;
-  if (p.payload_dtype == MVP_BF16)
-    hipLaunchKernelGGL(k_march_fwd<true>, dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
-                       (float4 *)rgba, aux, counters);
-  else
-    hipLaunchKernelGGL(k_march_fwd<false>, dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
-                       (float4 *)rgba, aux, counters);
+  const bool win = fwd_windows();
+  if (p.payload_dtype == MVP_BF16) {
+    if (win)
+      hipLaunchKernelGGL((k_march_fwd<true, true>), dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
+                         (float4 *)rgba, aux, counters);
+    else
+      hipLaunchKernelGGL((k_march_fwd<true, false>), dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
+                         (float4 *)rgba, aux, counters);
+  } else {
+    if (win)
+      hipLaunchKernelGGL((k_march_fwd<false, true>), dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
+                         (float4 *)rgba, aux, counters);
+    else
+      hipLaunchKernelGGL((k_march_fwd<false, false>), dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
+                         (float4 *)rgba, aux, counters);
+  }
   return hipGetLastError();
 }
 
