@@ -133,13 +133,25 @@ const char *mvp_version(void);
 mvp_status mvp_build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams,
                            int32_t n_views, const mvp_march_params *params,
                            mvp_accel **out, void *stream);
+/* The same for a subset of the rays: the training mode of Sec. 3.3, where each
+ * iteration samples rays from the images.  rays is a DEVICE array of n_rays
+ * pixel ids, id = (view * height + py) * width + px, in any order (the library
+ * keeps a copy); a pixel may appear more than once as long as no 16x16 tile
+ * receives more than 256 rays.  Forward and backward then read and write
+ * per-ray arrays in the order of `rays`: rgba [n_rays,4], aux [n_rays],
+ * grad_rgba [n_rays,4].  Out-of-range ids fail with MVP_ERR_INVALID.  BLOCKS
+ * like mvp_build_accel. */
+mvp_status mvp_build_accel_rays(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams,
+                                int32_t n_views, const mvp_march_params *params, const int64_t *rays,
+                                int64_t n_rays, mvp_accel **out, void *stream);
 /* Release an acceleration structure.  Its memory is recycled only after the
  * work already enqueued on `stream` has finished. */
 mvp_status mvp_accel_destroy(mvp_ctx *ctx, mvp_accel *accel, void *stream);
 mvp_status mvp_accel_get_info(const mvp_accel *accel, mvp_accel_info *info);
 
 /* Forward march (Sec. 3.2.2).  prims must be the primitives the structure was
- * built from (payload may differ).  Writes
+ * built from (payload may differ).  Writes, per ray (per pixel, or per entry of
+ * the ray subset):
  *   rgba [n_views,H,W,4] float32: premultiplied colour I and alpha A per pixel,
  *   aux  [n_views,H,W]   mvp_ray_aux (may be NULL if no backward follows).
  * Deterministic: each pixel is written by one thread in a fixed order. */

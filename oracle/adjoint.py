@@ -29,17 +29,29 @@ from __future__ import annotations
 
 import numpy as np
 
-from .render import render
+from .render import fade_window, render
 
 F64 = np.float64
 
 
-def render_grad(prims, cam, params, grad_rgba, pixels=None, geometry="fp32"):
+def render_grad(prims, cam, params, grad_rgba, pixels=None, geometry="fp32", background=None):
     """Forward of ``render`` plus the gradient of L = sum(grad_rgba * rgba).
+
+    With a fade window (params.fade_alpha > 0) the payload gradient is with
+    respect to the stored payload, i.e. multiplied by the window on the opacity
+    channel.  With a background B [R,3] the output colour is I + (1 - A) B, so
+    the upstream of I is g and the upstream of A is h - g . B; grads then also
+    hold "background" = (1 - A) g.
 
     Returns (forward dict, grads) where grads has
       payload [N,M,M,M,4], pos [N,3], rot [N,3,3], scale [N,3]  (FP64)."""
-    out = render(prims, cam, params, pixels, geometry, _want_grad=True)
+    out = render(prims, cam, params, pixels, geometry, _want_grad=True, background=background)
+    if background is not None:
+        grad_rgba = np.array(grad_rgba, dtype=F64).reshape(-1, 4)
+        bgr = np.asarray(background, dtype=F64).reshape(-1, 3)
+        a_pm = out["rgba_premultiplied"][:, 3]
+        g_bg = (1.0 - a_pm)[:, None] * grad_rgba[:, :3]
+        grad_rgba[:, 3] = grad_rgba[:, 3] - np.einsum("ij,ij->i", grad_rgba[:, :3], bgr)
     A32, tr, g_sig, g_col, rb, last_group = out.pop("_internal")
     n, M = prims.n, prims.m
     gpay = np.zeros(n * M * M * M * 4)
@@ -50,6 +62,8 @@ def render_grad(prims, cam, params, grad_rgba, pixels=None, geometry="fp32"):
     R = out["rgba"].shape[0]
     gr = np.asarray(grad_rgba, dtype=F64).reshape(R, 4)
     ntr = tr["ray"].size
+    if background is not None:
+        grads["background"] = g_bg
     if ntr == 0:
         grads["payload"] = gpay.reshape(n, M, M, M, 4)
         return out, grads
@@ -91,6 +105,9 @@ def render_grad(prims, cam, params, grad_rgba, pixels=None, geometry="fp32"):
         for ch in range(4):
             np.add.at(gpay, base + ch, wgt * adj[:, ch])
     grads["payload"] = gpay.reshape(n, M, M, M, 4)
+    alpha = float(getattr(params, "fade_alpha", 0.0) or 0.0)
+    if alpha != 0.0:
+        grads["payload"][..., 3] *= fade_window(M, alpha, float(getattr(params, "fade_beta", 8.0)))[None]
 
     # pose: through y = diag(1/s) R^T (o + tau d - t)
     gy = np.einsum("ic,icd->id", adj, tr["dval"])                    # [ntr,3]

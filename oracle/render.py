@@ -222,7 +222,36 @@ def accumulate(sig, col, dt, eps):
     return np.array(I), T, last, t_prev, margin
 
 
-def render(prims, cam, params, pixels=None, geometry="fp32", _want_grad=False):
+def fade_window(M, alpha, beta):
+    """Opacity fade window of Sec. 3.1.3 at the voxel centres,
+    W(x, y, z) = exp(-alpha (|x|^beta + |y|^beta + |z|^beta)) with (x, y, z) the
+    normalised voxel coordinates in [-1, 1]^3; returned as [iz][iy][ix] (FP64)."""
+    x = -1.0 + 2.0 * np.arange(M) / (M - 1)
+    p = np.abs(x) ** beta
+    return np.exp(-alpha * (p[:, None, None] + p[None, :, None] + p[None, None, :]))
+
+
+def windowed(prims, params):
+    """Primitives whose opacity channel is multiplied by the fade window
+    (identity when params.fade_alpha is 0 or absent)."""
+    alpha = float(getattr(params, "fade_alpha", 0.0) or 0.0)
+    if alpha == 0.0:
+        return prims
+    beta = float(getattr(params, "fade_beta", 8.0))
+    pay = prims.payload.astype(F64)
+    pay[..., 3] = pay[..., 3] * fade_window(prims.m, alpha, beta)[None]
+    return type(prims)(prims.pos, prims.rot, prims.scale, pay, getattr(prims, "bf16", False))
+
+
+def composite_background(rgba, background):
+    """Composite the premultiplied render over a background:
+    colour I + (1 - A) B, alpha A."""
+    out = rgba.copy()
+    out[:, :3] = rgba[:, :3] + (1.0 - rgba[:, 3:4]) * np.asarray(background, dtype=F64).reshape(-1, 3)
+    return out
+
+
+def render(prims, cam, params, pixels=None, geometry="fp32", _want_grad=False, background=None):
     """Render the rays of one camera (all pixels, or the (py, px) list given).
 
     Returns a dict with
@@ -233,7 +262,7 @@ def render(prims, cam, params, pixels=None, geometry="fp32", _want_grad=False):
       prim_samples  [R]          (sample, primitive) pairs up to the stop
       margin        [R]          closest distance of a clamp/stop decision to its threshold
     """
-    d, A, tr, g_sig, g_col, rb = _samples(prims, cam, params, pixels, geometry, _want_grad)
+    d, A, tr, g_sig, g_col, rb = _samples(windowed(prims, params), cam, params, pixels, geometry, _want_grad)
     R = d.shape[0]
     rgba = np.zeros((R, 4))
     j_end = np.full(R, -1, dtype=np.int64)
@@ -259,6 +288,9 @@ def render(prims, cam, params, pixels=None, geometry="fp32", _want_grad=False):
     prim_samples = np.bincount(tr["ray"][in_use], minlength=R) if R else np.zeros(0, dtype=np.int64)
     out = {"rgba": rgba, "j_end": j_end, "t_prev": t_prev, "ray_samples": ray_samples,
            "prim_samples": prim_samples, "margin": margin, "dirs": d}
+    if background is not None:
+        out["rgba_premultiplied"] = rgba
+        out["rgba"] = composite_background(rgba, background)
     if _want_grad:
         out["_internal"] = (A, tr, g_sig, g_col, rb, last_group)
     return out

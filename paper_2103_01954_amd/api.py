@@ -95,21 +95,37 @@ class Context:
             self.handle = None
 
     def build_accel(self, prims: DevicePrims, cams: Sequence[Camera], params: MarchParams,
-                    stream=None) -> "Accel":
+                    stream=None, rays: Optional[torch.Tensor] = None) -> "Accel":
+        """Culling lists and per-ray pair lists for every pixel of every view, or
+        for the pixel ids in `rays` (int64 device tensor, id = (v*H + py)*W + px)."""
         arr = (L.mvp_camera * len(cams))(*[c_camera(c) for c in cams])
         cp = prims.c_struct()
         pp = c_params(params)
         h = C.c_void_p()
-        L.check("mvp_build_accel", self.lib.mvp_build_accel(self.handle, C.byref(cp), arr, len(cams),
-                                                            C.byref(pp), C.byref(h), _stream(stream)))
-        return Accel(self, h, len(cams), cams[0].height, cams[0].width, _stream(stream))
+        if rays is None:
+            L.check("mvp_build_accel", self.lib.mvp_build_accel(self.handle, C.byref(cp), arr, len(cams),
+                                                                C.byref(pp), C.byref(h), _stream(stream)))
+            return Accel(self, h, len(cams), cams[0].height, cams[0].width, _stream(stream))
+        if rays.dtype != torch.int64 or not rays.is_cuda or rays.dim() != 1:
+            raise ValueError("rays must be a 1-D int64 CUDA tensor of pixel ids")
+        rays = rays.contiguous()
+        L.check("mvp_build_accel_rays", self.lib.mvp_build_accel_rays(
+            self.handle, C.byref(cp), arr, len(cams), C.byref(pp), rays.data_ptr(), rays.numel(), C.byref(h),
+            _stream(stream)))
+        return Accel(self, h, len(cams), cams[0].height, cams[0].width, _stream(stream), n_rays=rays.numel())
 
 
 class Accel:
-    def __init__(self, ctx: Context, handle, views: int, height: int, width: int, stream: int = 0):
+    def __init__(self, ctx: Context, handle, views: int, height: int, width: int, stream: int = 0,
+                 n_rays: Optional[int] = None):
         self.ctx, self.handle = ctx, handle
         self.views, self.height, self.width = views, height, width
         self.stream = stream      # stream of the build; default for destroy
+        self.n_rays = n_rays      # ray-subset size, None for full frames
+
+    @property
+    def ray_shape(self):
+        return (self.views, self.height, self.width) if self.n_rays is None else (self.n_rays,)
 
     def __del__(self):
         try:
@@ -132,7 +148,7 @@ class Accel:
 
     def render_fwd(self, prims: DevicePrims, rgba: Optional[torch.Tensor] = None,
                    aux: Optional[torch.Tensor] = None, want_aux: bool = True, stream=None):
-        shape = (self.views, self.height, self.width)
+        shape = self.ray_shape
         dev = prims.pos.device
         if rgba is None:
             rgba = torch.empty(shape + (4,), dtype=torch.float32, device=dev)
@@ -168,7 +184,7 @@ class Accel:
 
     def debug_hits(self, prims: DevicePrims, stream=None):
         """Per-ray sorted hit sets as (offsets [R+1] int64, ids int32) numpy arrays."""
-        R = self.views * self.height * self.width
+        R = int(np.prod(self.ray_shape))
         dev = prims.pos.device
         off = torch.empty(R + 1, dtype=torch.int64, device=dev)
         cap = C.c_int64(0)

@@ -234,7 +234,8 @@ static mvp_status read_u64(const uint64_t *dev, uint64_t *host, hipStream_t s) {
 }
 
 mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams, int32_t n_views,
-                       const mvp_march_params *params, mvp_accel **out, hipStream_t s, const Admit *admit) {
+                       const mvp_march_params *params, const int64_t *rays, int64_t n_rays,
+                       mvp_accel **out, hipStream_t s, const Admit *admit) {
   if (!ctx || !out || !cams) { set_error("NULL argument"); return MVP_ERR_INVALID; }
   *out = nullptr;
   MVP_CHECK(check_prims(prims, false));
@@ -250,12 +251,17 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   const int W = cams[0].width, H = cams[0].height, N = prims->n_prim;
   const int tx = (W + kTile - 1) / kTile, ty = (H + kTile - 1) / kTile;
   const size_t ntile = (size_t)n_views * tx * ty;
-  const size_t R = (size_t)n_views * W * H;
+  const size_t npix = (size_t)n_views * W * H;
+  if (rays && n_rays < 0) { set_error("n_rays < 0"); return MVP_ERR_INVALID; }
+  if (!rays && n_rays != 0) { set_error("rays is NULL"); return MVP_ERR_INVALID; }
+  const size_t R = rays ? (size_t)n_rays : npix;   // ray slots
   if (ntile >= (size_t)1 << 31) { set_error("too many tiles"); return MVP_ERR_INVALID; }
+  if (R >= (size_t)1 << 31) { set_error("too many rays (%zu) in one structure", R); return MVP_ERR_INVALID; }
 
   mvp_accel *a = new (std::nothrow) mvp_accel();
   if (!a) { set_error("host allocation failed"); return MVP_ERR_OOM; }
   a->ctx = ctx; a->V = n_views; a->W = W; a->H = H; a->N = N; a->tiles_x = tx; a->tiles_y = ty;
+  a->n_slots = (int64_t)R;
   a->params = *params;
   a->cams_host.resize(n_views);
   for (int v = 0; v < n_views; ++v) {
@@ -279,12 +285,13 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   MVP_HIP(hipSetDevice(ctx->device));
   Blocks keep{ctx, s}, temp{ctx, s};
   int4 *rect = nullptr;
-  uint32_t *tile_cnt = nullptr, *ray_cnt = nullptr;
-  void *scratch = nullptr;
+  uint32_t *tile_cnt = nullptr, *ray_cnt = nullptr, *entry_cnt = nullptr;
+  uint8_t *scratch = nullptr, *scratch2 = nullptr;
   const size_t sb = scan_scratch_bytes(ntile > R ? ntile : R);
   if (admit) {
     const size_t base = n_views * sizeof(DevCam) + 3 * (size_t)N * 16 + (ntile + 1) * 8 + (R + 1) * 8 + 16 +
-                        (size_t)n_views * N * 16 + ntile * 4 + R * 4 + sb + 9 * 256;
+                        (size_t)n_views * N * 16 + ntile * 4 + R * 4 + sb + 9 * 256 +
+                        (rays ? R * 12 + ntile * 12 + 3 * 256 : 0);
     MVP_CHECK(admit->fn(admit->user, base));
   }
   MVP_CHECK(keep.get(&a->cams, n_views));
@@ -295,42 +302,79 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   MVP_CHECK(temp.get(&rect, (size_t)n_views * N));
   MVP_CHECK(temp.get(&tile_cnt, ntile));
   MVP_CHECK(temp.get(&ray_cnt, R));
-  {
-    uint8_t *sp = nullptr;
-    MVP_CHECK(temp.get(&sp, sb));
-    scratch = sp;
-  }
+  MVP_CHECK(temp.get(&scratch, sb));
   MVP_HIP(hipMemcpyAsync(a->cams, a->cams_host.data(), n_views * sizeof(DevCam), hipMemcpyHostToDevice, s));
+  uint32_t *flag = nullptr;
+  if (rays) {
+    // ray subset: a private copy of the pixel ids, binned into screen tiles
+    uint32_t *rcnt = nullptr;
+    MVP_CHECK(keep.get(&a->ray_pix, R ? R : 1));
+    MVP_CHECK(keep.get(&a->tile_ray_off, ntile + 1));
+    MVP_CHECK(keep.get(&a->tile_rays, R ? R : 1));
+    MVP_CHECK(temp.get(&rcnt, ntile));
+    MVP_CHECK(temp.get(&flag, 1));
+    if (R) MVP_HIP(hipMemcpyAsync(a->ray_pix, rays, R * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    AccelView rv = a->view(2);
+    MVP_HIP(launch_zero_u32(rcnt, ntile, s));
+    MVP_HIP(launch_zero_u32(flag, 1, s));
+    MVP_HIP(launch_ray_bin(rv, rcnt, flag, s));
+    MVP_HIP(launch_scan_u32_u64(rcnt, a->tile_ray_off, ntile, scratch, s));
+    MVP_HIP(launch_zero_u32(rcnt, ntile, s));
+    MVP_HIP(launch_ray_fill(rv, rcnt, a->tile_rays, s));
+    MVP_HIP(launch_segment_sort(a->tile_ray_off, a->tile_rays, (int64_t)ntile, s));
+  }
   AccelView av = a->view(2);
 
-  // culling lists
+  // culling lists: rectangles, tile counts, offsets, fill, sort by primitive id
   MVP_HIP(launch_zero_u32(tile_cnt, ntile, s));
   MVP_HIP(launch_prep(*prims, av, a->xf, rect, tile_cnt, s));
   MVP_HIP(launch_scan_u32_u64(tile_cnt, a->tile_off, ntile, scratch, s));
   uint64_t n_tile_pairs = 0;
+  uint32_t flag_h = 0;
+  if (flag) MVP_HIP(hipMemcpyAsync(&flag_h, flag, sizeof flag_h, hipMemcpyDeviceToHost, s));
   MVP_CHECK(read_u64(a->tile_off + ntile, &n_tile_pairs, s));
-  if (admit) MVP_CHECK(admit->fn(admit->user, n_tile_pairs * 4 + 256));
-  MVP_CHECK(keep.get(&a->tile_list, n_tile_pairs ? n_tile_pairs : 1));
+  if (flag_h & 1u) { set_error("a ray pixel id is outside [0, n_views*height*width)"); return MVP_ERR_INVALID; }
+  if (flag_h & 2u) { set_error("more than 256 rays in one 16x16 tile (repeated pixel ids)"); return MVP_ERR_INVALID; }
+  const size_t ntp = n_tile_pairs ? n_tile_pairs : 1;
+  const size_t sb2 = scan_scratch_bytes(n_tile_pairs);
+  if (admit) MVP_CHECK(admit->fn(admit->user, ntp * 20 + 8 + sb2 + 4 * 256));
+  MVP_CHECK(keep.get(&a->tile_list, ntp));
+  MVP_CHECK(keep.get(&a->entry_tile, ntp));
+  MVP_CHECK(keep.get(&a->entry_off, ntp + 1));
+  MVP_CHECK(temp.get(&entry_cnt, ntp));
+  MVP_CHECK(temp.get(&scratch2, sb2));
   av = a->view(2);
   MVP_HIP(launch_zero_u32(tile_cnt, ntile, s));
-  MVP_HIP(launch_tile_fill(av, rect, tile_cnt, a->tile_list, s));
+  MVP_HIP(launch_tile_fill(av, rect, tile_cnt, a->tile_list, a->entry_tile, s));
+  MVP_HIP(launch_segment_sort(a->tile_off, a->tile_list, (int64_t)ntile, s));
 
-  // per-ray pair lists
-  MVP_HIP(launch_hit_count(av, 0, ray_cnt, s));
+  // per-ray pair counts and per-entry counts, offsets
+  MVP_HIP(launch_hit_count(av, 0, ray_cnt, entry_cnt, s));
   MVP_HIP(launch_scan_u32_u64(ray_cnt, a->ray_off, R, scratch, s));
+  MVP_HIP(launch_scan_u32_u64(entry_cnt, a->entry_off, n_tile_pairs, scratch2, s));
   uint64_t n_pairs = 0;
   MVP_CHECK(read_u64(a->ray_off + R, &n_pairs, s));
-  if (admit) MVP_CHECK(admit->fn(admit->user, n_pairs * 36 + 3 * 256));
-  MVP_CHECK(keep.get(&a->pa, n_pairs ? n_pairs : 1));
-  MVP_CHECK(keep.get(&a->pb, n_pairs ? n_pairs : 1));
-  MVP_CHECK(keep.get(&a->pid, n_pairs ? n_pairs : 1));
+  if (n_pairs >= (uint64_t)1 << 32) { set_error("%llu ray/primitive pairs exceed 2^32", (unsigned long long)n_pairs); return MVP_ERR_INVALID; }
+  const size_t np = n_pairs ? n_pairs : 1;
+  if (admit) MVP_CHECK(admit->fn(admit->user, np * 88 + 8 * 256));
+  float4 *tpa = nullptr, *tpb = nullptr;
+  int2 *tpj = nullptr;
+  uint32_t *perm = nullptr;
+  MVP_CHECK(keep.get(&a->pa, np));
+  MVP_CHECK(keep.get(&a->pb, np));
+  MVP_CHECK(keep.get(&a->pj, np));
+  MVP_CHECK(keep.get(&a->entry_pairs, np));
+  MVP_CHECK(temp.get(&tpa, np));
+  MVP_CHECK(temp.get(&tpb, np));
+  MVP_CHECK(temp.get(&tpj, np));
+  MVP_CHECK(temp.get(&perm, np));
   av = a->view(2);
-  MVP_HIP(launch_hit_emit(av, 0, a->pa, a->pb, a->pid, s));
+  MVP_HIP(launch_hit_emit(av, 0, tpa, tpb, tpj, a->pa, a->pb, a->pj, perm, a->entry_pairs, nullptr, n_pairs, s));
 
   a->n_tile_pairs = (int64_t)n_tile_pairs;
   a->n_ray_pairs = (int64_t)n_pairs;
   a->bytes = (int64_t)(n_views * sizeof(DevCam) + 3 * (size_t)N * 16 + (ntile + 1) * 8 + (R + 1) * 8 +
-                       n_tile_pairs * 4 + n_pairs * 36);
+                       n_tile_pairs * 16 + n_pairs * 44 + (rays ? R * 12 + (ntile + 1) * 8 : 0));
   a->blocks = keep.list;
   keep.keep = true;
   // temporaries are recycled once the emit kernel has run
@@ -394,7 +438,14 @@ mvp_status mvp_destroy(mvp_ctx *ctx) {
 
 mvp_status mvp_build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams, int32_t n_views,
                            const mvp_march_params *params, mvp_accel **out, void *stream) {
-  return build_accel(ctx, prims, cams, n_views, params, out, (hipStream_t)stream, nullptr);
+  return build_accel(ctx, prims, cams, n_views, params, nullptr, 0, out, (hipStream_t)stream, nullptr);
+}
+
+mvp_status mvp_build_accel_rays(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams, int32_t n_views,
+                                const mvp_march_params *params, const int64_t *rays, int64_t n_rays,
+                                mvp_accel **out, void *stream) {
+  if (!rays) { set_error("rays is NULL"); return MVP_ERR_INVALID; }
+  return build_accel(ctx, prims, cams, n_views, params, rays, n_rays, out, (hipStream_t)stream, nullptr);
 }
 
 mvp_status mvp_accel_destroy(mvp_ctx *ctx, mvp_accel *accel, void *stream) {
@@ -411,7 +462,7 @@ mvp_status mvp_accel_get_info(const mvp_accel *a, mvp_accel_info *info) {
 mvp_status mvp_render_fwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims, float *rgba,
                           mvp_ray_aux *aux, void *stream) {
   MVP_CHECK(check_render(ctx, a, prims));
-  if (!rgba) { set_error("rgba is NULL"); return MVP_ERR_INVALID; }
+  if (!rgba && a->n_slots > 0) { set_error("rgba is NULL"); return MVP_ERR_INVALID; }
   hipStream_t s = (hipStream_t)stream;
   MVP_HIP(hipSetDevice(ctx->device));
   MVP_HIP(launch_zero_u64((uint64_t *)a->counters, 2, s));
@@ -423,12 +474,15 @@ mvp_status mvp_render_bwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *pri
                           const float *grad_rgba, float *grad_payload, float *grad_pos, float *grad_rot,
                           float *grad_scale, void *stream) {
   MVP_CHECK(check_render(ctx, a, prims));
-  if (!aux || !grad_rgba) { set_error("aux and grad_rgba are required"); return MVP_ERR_INVALID; }
+  if ((!aux || !grad_rgba) && a->n_slots > 0) { set_error("aux and grad_rgba are required"); return MVP_ERR_INVALID; }
   hipStream_t s = (hipStream_t)stream;
   MVP_HIP(hipSetDevice(ctx->device));
-  MVP_HIP(launch_march_bwd(a->view(prims->M), *prims, aux, grad_rgba, grad_payload, grad_pos, grad_rot,
-                           grad_scale, s));
-  return MVP_OK;
+  Blocks temp{ctx, s};
+  float2 *rc = nullptr;
+  MVP_CHECK(temp.get(&rc, a->n_rays()));
+  MVP_HIP(launch_march_bwd(a->view(prims->M), *prims, a->n_tile_pairs, aux, grad_rgba, rc, grad_payload,
+                           grad_pos, grad_rot, grad_scale, s));
+  return MVP_OK;   // the scratch is recycled after the kernels have run
 }
 
 mvp_status mvp_accel_counts(mvp_ctx *ctx, const mvp_accel *a, uint64_t *ray_samples, uint64_t *prim_samples,
@@ -458,7 +512,7 @@ mvp_status mvp_debug_hits(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *pri
   MVP_CHECK(temp.get(&cnt, R));
   MVP_CHECK(temp.get(&scratch, scan_scratch_bytes(R)));
   AccelView av = a->view(prims->M);
-  MVP_HIP(launch_hit_count(av, 1, cnt, s));
+  MVP_HIP(launch_hit_count(av, 1, cnt, nullptr, s));
   MVP_HIP(launch_scan_u32_u64(cnt, (uint64_t *)offsets, R, scratch, s));
   uint64_t total = 0;
   MVP_CHECK(read_u64((const uint64_t *)offsets + R, &total, s));
@@ -466,7 +520,7 @@ mvp_status mvp_debug_hits(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *pri
   if ((int64_t)total > ids_cap) { set_error("ids_cap %lld < %llu hits", (long long)ids_cap, (unsigned long long)total); return MVP_ERR_OOM; }
   if (total > 0 && !ids) { set_error("ids is NULL"); return MVP_ERR_INVALID; }
   av.ray_off = (const uint64_t *)offsets;
-  MVP_HIP(launch_hit_emit(av, 1, nullptr, nullptr, ids, s));
+  MVP_HIP(launch_hit_emit(av, 1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ids, 0, s));
   MVP_HIP(hipStreamSynchronize(s));
   return MVP_OK;
 }

@@ -68,9 +68,16 @@ struct mvp_accel {
   float4 *xf = nullptr;
   uint64_t *tile_off = nullptr;
   uint32_t *tile_list = nullptr;
+  uint32_t *entry_tile = nullptr;
+  uint64_t *entry_off = nullptr;
+  uint32_t *entry_pairs = nullptr;
   uint64_t *ray_off = nullptr;
   float4 *pa = nullptr, *pb = nullptr;
-  int32_t *pid = nullptr;
+  int2 *pj = nullptr;
+  int64_t n_slots = 0;                 // rays: V*H*W (full frames) or the subset size
+  int64_t *ray_pix = nullptr;          // subset only: pixel id of each ray slot
+  uint64_t *tile_ray_off = nullptr;    // subset only
+  uint32_t *tile_rays = nullptr;       // subset only
   unsigned long long *counters = nullptr;
   int64_t n_tile_pairs = 0, n_ray_pairs = 0, bytes = 0;
   std::vector<void *> blocks;
@@ -81,10 +88,12 @@ struct mvp_accel {
     v.tiles_x = tiles_x; v.tiles_y = tiles_y;
     v.step = params.step; v.eps = params.eps_early; v.t_near = params.t_near;
     v.cams = cams; v.xf = xf; v.tile_off = tile_off; v.tile_list = tile_list;
-    v.ray_off = ray_off; v.pa = pa; v.pb = pb; v.pid = pid;
+    v.entry_tile = entry_tile; v.entry_off = entry_off; v.entry_pairs = entry_pairs;
+    v.ray_off = ray_off; v.pa = pa; v.pb = pb; v.pj = pj;
+    v.n_slots = n_slots; v.ray_pix = ray_pix; v.tile_ray_off = tile_ray_off; v.tile_rays = tile_rays;
     return v;
   }
-  size_t n_rays() const { return (size_t)V * H * W; }
+  size_t n_rays() const { return (size_t)n_slots; }
 };
 
 namespace mvp {
@@ -99,8 +108,10 @@ struct Admit {
   mvp_status (*fn)(void *user, size_t bytes);
   void *user;
 };
+// rays == nullptr: every pixel of every view; else n_rays device pixel ids
 mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams, int32_t n_views,
-                       const mvp_march_params *params, mvp_accel **out, hipStream_t s, const Admit *admit);
+                       const mvp_march_params *params, const int64_t *rays, int64_t n_rays,
+                       mvp_accel **out, hipStream_t s, const Admit *admit);
 mvp_status destroy_accel(mvp_ctx *ctx, mvp_accel *a, hipStream_t s);
 // stop the serving scheduler of a context (waits for its work)
 void serve_shutdown(mvp_ctx *ctx);

@@ -20,6 +20,8 @@
 //              integration (Sec. 3.2.1).
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "internal.h"
 
 namespace mvp {
@@ -347,7 +349,8 @@ hipError_t launch_prep(const mvp_prims &p, const AccelView &av, float4 *xf, int4
 
 __global__ __launch_bounds__(256) void k_tile_fill(AccelView av, const int4 *__restrict__ rect,
                                                    uint32_t *__restrict__ cursor,
-                                                   uint32_t *__restrict__ list) {
+                                                   uint32_t *__restrict__ list,
+                                                   uint32_t *__restrict__ entry_tile) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (size_t)av.V * av.N) return;
   const int v = (int)(i / av.N);
@@ -359,15 +362,127 @@ __global__ __launch_bounds__(256) void k_tile_fill(AccelView av, const int4 *__r
       const size_t tile = (size_t)v * T + (size_t)ty * av.tiles_x + tx;
       const uint32_t slot = atomicAdd(&cursor[tile], 1u);
       list[av.tile_off[tile] + slot] = (uint32_t)k;
+      entry_tile[av.tile_off[tile] + slot] = (uint32_t)tile;
     }
 }
 
 hipError_t launch_tile_fill(const AccelView &av, const int4 *rect, uint32_t *cursor,
-                            uint32_t *tile_list, hipStream_t s) {
+                            uint32_t *tile_list, uint32_t *entry_tile, hipStream_t s) {
   const size_t n = (size_t)av.V * av.N;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, av, rect, cursor,
-                     tile_list);
+                     tile_list, entry_tile);
+  return hipGetLastError();
+}
+
+// Sort every tile's culling list by primitive id, so that the list order (and
+// with it the order of every per-ray list and of every floating-point sum over
+// a sample's primitives) does not depend on the order of the fill atomics.
+// Bitonic sort in LDS; lists longer than kSortMax fall back to a heapsort by
+// one thread.
+constexpr int kSortMax = 4096;
+
+__global__ __launch_bounds__(256) void k_segment_sort(const uint64_t *__restrict__ off,
+                                                      uint32_t *__restrict__ list) {
+  __shared__ uint32_t s[kSortMax];
+  const int64_t seg = blockIdx.x;
+  const uint64_t b = off[seg];
+  const int64_t n = (int64_t)(off[seg + 1] - b);
+  if (n < 2) return;
+  if (n <= kSortMax) {
+    int np = 2;
+    while (np < n) np <<= 1;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s[i] = i < n ? list[b + i] : 0xffffffffu;
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < np; i += blockDim.x) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const uint32_t x = s[i], y = s[ixj];
+            const bool up = (i & k) == 0;
+            if ((x > y) == up) {
+              s[i] = y;
+              s[ixj] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) list[b + i] = s[i];
+    return;
+  }
+  if (threadIdx.x != 0) return;
+  uint32_t *a = list + b;
+  auto sift = [&](int64_t root, int64_t end) {
+    while (2 * root + 1 < end) {
+      int64_t child = 2 * root + 1;
+      if (child + 1 < end && a[child] < a[child + 1]) ++child;
+      if (a[root] < a[child]) {
+        const uint32_t t = a[root]; a[root] = a[child]; a[child] = t;
+        root = child;
+      } else {
+        return;
+      }
+    }
+  };
+  for (int64_t i = n / 2; i-- > 0;) sift(i, n);
+  for (int64_t end = n - 1; end > 0; --end) {
+    const uint32_t t = a[0]; a[0] = a[end]; a[end] = t;
+    sift(0, end);
+  }
+}
+
+hipError_t launch_segment_sort(const uint64_t *off, uint32_t *data, int64_t n_seg, hipStream_t s) {
+  if (n_seg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_segment_sort, dim3((unsigned)n_seg), dim3(256), 0, s, off, data);
+  return hipGetLastError();
+}
+
+// Ray subsets: bin the sampled rays (pixel ids) into screen tiles.
+__global__ __launch_bounds__(256) void k_ray_bin(AccelView av, uint32_t *__restrict__ tile_cnt,
+                                                 uint32_t *__restrict__ flag) {
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= av.n_slots) return;
+  const int64_t pix = av.ray_pix[slot];
+  if (pix < 0 || pix >= (int64_t)av.V * av.W * av.H) {
+    atomicOr(flag, 1u);
+    return;
+  }
+  const int64_t hw = (int64_t)av.W * av.H;
+  const int v = (int)(pix / hw);
+  const int64_t r = pix - v * hw;
+  const int px = (int)(r % av.W), py = (int)(r / av.W);
+  const size_t tile = (size_t)v * av.tiles_x * av.tiles_y + (size_t)(py / kTile) * av.tiles_x + px / kTile;
+  if (atomicAdd(&tile_cnt[tile], 1u) >= (uint32_t)kTileThreads) atomicOr(flag, 2u);
+}
+
+__global__ __launch_bounds__(256) void k_ray_fill(AccelView av, uint32_t *__restrict__ cursor,
+                                                  uint32_t *__restrict__ tile_rays) {
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= av.n_slots) return;
+  const int64_t pix = av.ray_pix[slot];
+  if (pix < 0 || pix >= (int64_t)av.V * av.W * av.H) return;
+  const int64_t hw = (int64_t)av.W * av.H;
+  const int v = (int)(pix / hw);
+  const int64_t r = pix - v * hw;
+  const int px = (int)(r % av.W), py = (int)(r / av.W);
+  const size_t tile = (size_t)v * av.tiles_x * av.tiles_y + (size_t)(py / kTile) * av.tiles_x + px / kTile;
+  const uint32_t k = atomicAdd(&cursor[tile], 1u);
+  const uint64_t pos = av.tile_ray_off[tile] + k;
+  if (pos < av.tile_ray_off[tile + 1]) tile_rays[pos] = (uint32_t)slot;
+}
+
+hipError_t launch_ray_bin(const AccelView &av, uint32_t *tile_cnt, uint32_t *flag, hipStream_t s) {
+  if (av.n_slots == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ray_bin, dim3((unsigned)((av.n_slots + 255) / 256)), dim3(256), 0, s, av, tile_cnt, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_ray_fill(const AccelView &av, uint32_t *cursor, uint32_t *tile_rays, hipStream_t s) {
+  if (av.n_slots == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ray_fill, dim3((unsigned)((av.n_slots + 255) / 256)), dim3(256), 0, s, av, cursor, tile_rays);
   return hipGetLastError();
 }
 
@@ -422,21 +537,20 @@ __device__ inline bool pair_of(const Staged &sm, int e, const float d[3], float 
   return *jlo <= *jhi;
 }
 
-__device__ inline void tile_pixel(const AccelView &av, int tile, int *v, int *px, int *py) {
-  const int T = av.tiles_x * av.tiles_y;
-  *v = tile / T;
-  const int tt = tile % T;
-  *px = (tt % av.tiles_x) * kTile + (threadIdx.x % kTile);
-  *py = (tt / av.tiles_x) * kTile + (threadIdx.x / kTile);
-}
 
+// Count kernel: per ray the number of pairs (mode 0: pairs with >= 1 sample;
+// mode 1: slab hits), and in mode 0 per culling-list entry the number of the
+// tile's rays that form a pair with it (entry_cnt, indexed like tile_list).
 __global__ __launch_bounds__(kTileThreads) void k_hit_count(AccelView av, int mode,
-                                                             uint32_t *__restrict__ ray_cnt) {
+                                                             uint32_t *__restrict__ ray_cnt,
+                                                             uint32_t *__restrict__ entry_cnt) {
   __shared__ Staged sm;
+  __shared__ uint32_t s_cnt[kTileThreads / kWave][kStage];
   const int tile = blockIdx.x;
   int v, px, py;
-  tile_pixel(av, tile, &v, &px, &py);
-  const bool valid = px < av.W && py < av.H;
+  size_t slot;
+  const bool valid = tile_ray(av, tile, threadIdx.x, &slot, &v, &px, &py);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const DevCam &cam = av.cams[v];
   float d[3];
   pixel_ray(cam, px, py, d);
@@ -447,133 +561,163 @@ __global__ __launch_bounds__(kTileThreads) void k_hit_count(AccelView av, int mo
     __syncthreads();
     stage_chunk(sm, av, cam, c0, n);
     __syncthreads();
-    if (valid) {
-      for (int e = 0; e < n; ++e) {
-        float a[3], b[3];
-        int jlo, jhi;
-        cnt += pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi) ? 1u : 0u;
+    for (int e = 0; e < n; ++e) {
+      float a[3], b[3];
+      int jlo, jhi;
+      const bool hit = valid && pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi);
+      cnt += hit ? 1u : 0u;
+      if (mode == 0) {
+        const unsigned long long m = __ballot(hit);
+        if (lane == 0) s_cnt[wave][e] = (uint32_t)__popcll(m);
+      }
+    }
+    if (mode == 0) {
+      __syncthreads();
+      if ((int)threadIdx.x < n) {
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < kTileThreads / kWave; ++w) tot += s_cnt[w][threadIdx.x];
+        entry_cnt[c0 + threadIdx.x] = tot;
       }
     }
   }
-  if (valid) ray_cnt[((size_t)v * av.H + py) * av.W + px] = cnt;
+  if (valid) ray_cnt[slot] = cnt;
 }
 
-hipError_t launch_hit_count(const AccelView &av, int mode, uint32_t *ray_cnt, hipStream_t s) {
+hipError_t launch_hit_count(const AccelView &av, int mode, uint32_t *ray_cnt, uint32_t *entry_cnt,
+                            hipStream_t s) {
   const int ntile = av.V * av.tiles_x * av.tiles_y;
   if (ntile == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hit_count, dim3(ntile), dim3(kTileThreads), 0, s, av, mode, ray_cnt);
+  hipLaunchKernelGGL(k_hit_count, dim3(ntile), dim3(kTileThreads), 0, s, av, mode, ray_cnt, entry_cnt);
   return hipGetLastError();
 }
 
-// ordering key of a pair: mode 0 (first sample, id), mode 1 (id)
-__device__ inline uint64_t pair_key(const float4 *pa, const int32_t *pid, uint64_t i, int mode) {
-  const uint64_t id = (uint32_t)pid[i];
-  if (mode == 1) return id;
-  return ((uint64_t)(uint32_t)__float_as_int(pa[i].w) << 32) | id;
-}
-
-__device__ inline void pair_move(float4 *pa, float4 *pb, int32_t *pid, uint64_t dst, uint64_t src, int mode) {
-  pid[dst] = pid[src];
-  if (mode == 0) {
-    pa[dst] = pa[src];
-    pb[dst] = pb[src];
-  }
-}
-
-// Sort one ray's segment [b, b+n) by key, in place: insertion sort for short
-// lists, heapsort otherwise.
-__device__ void sort_segment(float4 *pa, float4 *pb, int32_t *pid, uint64_t b, uint64_t n, int mode) {
-  if (n < 2) return;
-  if (n <= 32) {
-    for (uint64_t i = 1; i < n; ++i) {
-      const float4 ra = mode == 0 ? pa[b + i] : float4{};
-      const float4 rb = mode == 0 ? pb[b + i] : float4{};
-      const int32_t rid = pid[b + i];
-      const uint64_t key = mode == 1 ? (uint64_t)(uint32_t)rid
-                                     : (((uint64_t)(uint32_t)__float_as_int(ra.w) << 32) | (uint32_t)rid);
-      uint64_t j = i;
-      while (j > 0 && pair_key(pa, pid, b + j - 1, mode) > key) {
-        pair_move(pa, pb, pid, b + j, b + j - 1, mode);
-        --j;
-      }
-      pid[b + j] = rid;
-      if (mode == 0) {
-        pa[b + j] = ra;
-        pb[b + j] = rb;
-      }
-    }
-    return;
-  }
-  auto swap_at = [&](uint64_t x, uint64_t y) {
-    int32_t t = pid[b + x]; pid[b + x] = pid[b + y]; pid[b + y] = t;
-    if (mode == 0) {
-      float4 u = pa[b + x]; pa[b + x] = pa[b + y]; pa[b + y] = u;
-      float4 w = pb[b + x]; pb[b + x] = pb[b + y]; pb[b + y] = w;
-    }
-  };
-  auto sift = [&](uint64_t root, uint64_t end) {
-    while (2 * root + 1 < end) {
-      uint64_t child = 2 * root + 1;
-      if (child + 1 < end && pair_key(pa, pid, b + child, mode) < pair_key(pa, pid, b + child + 1, mode)) ++child;
-      if (pair_key(pa, pid, b + root, mode) < pair_key(pa, pid, b + child, mode)) {
-        swap_at(root, child);
-        root = child;
-      } else {
-        return;
-      }
-    }
-  };
-  for (uint64_t i = n / 2; i-- > 0;) sift(i, n);
-  for (uint64_t end = n - 1; end > 0; --end) {
-    swap_at(0, end);
-    sift(0, end);
-  }
-}
-
-__global__ __launch_bounds__(kTileThreads) void k_hit_emit(AccelView av, int mode, float4 *__restrict__ pa,
-                                                            float4 *__restrict__ pb,
-                                                            int32_t *__restrict__ pid) {
+// Emit kernel.  Each ray writes its pairs in culling-list order (which is
+// primitive-id order) into its segment [ray_off[ray], ray_off[ray+1]) of the
+// temporary arrays tpa/tpb/tpj:
+//   pa = (a, primitive id), pb = (b, ray index), pj = (jlo, jhi),
+// and, for every culling-list entry, the (temporary) indices of the pairs
+// formed with it (entry_pairs[entry_off[g] ..]), in pixel order, for the
+// backward's one-workgroup-per-entry reduction.  Then it moves its pairs to
+// pa/pb/pj sorted by (jlo, primitive id), the order the forward marches them
+// in, and records each pair's new index in perm (k_remap_pairs applies it to
+// entry_pairs).  Mode 1 writes only the primitive ids of the slab hits into
+// `ids`, in primitive-id order.
+__global__ __launch_bounds__(kTileThreads) void k_hit_emit(AccelView av, int mode, float4 *__restrict__ tpa,
+                                                            float4 *__restrict__ tpb, int2 *__restrict__ tpj,
+                                                            float4 *__restrict__ pa, float4 *__restrict__ pb,
+                                                            int2 *__restrict__ pj, uint32_t *__restrict__ perm,
+                                                            uint32_t *__restrict__ entry_pairs,
+                                                            int32_t *__restrict__ ids) {
   __shared__ Staged sm;
+  __shared__ uint32_t s_bits[kStage / 32][kTileThreads];
+  __shared__ uint32_t s_cnt[kTileThreads / kWave][kStage];
   const int tile = blockIdx.x;
   int v, px, py;
-  tile_pixel(av, tile, &v, &px, &py);
-  const bool valid = px < av.W && py < av.H;
+  size_t ray;
+  const bool valid = tile_ray(av, tile, threadIdx.x, &ray, &v, &px, &py);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const DevCam &cam = av.cams[v];
   float d[3];
   pixel_ray(cam, px, py, d);
-  const size_t ray = ((size_t)v * av.H + py) * av.W + px;
   const uint64_t out0 = valid ? av.ray_off[ray] : 0;
   const uint64_t out1 = valid ? av.ray_off[ray + 1] : 0;   // same predicate as the count pass
   uint64_t w = out0;
   const uint64_t lb = av.tile_off[tile], le = av.tile_off[tile + 1];
+  const unsigned long long lt = (1ull << lane) - 1ull;
   for (uint64_t c0 = lb; c0 < le; c0 += kStage) {
     const int n = (int)min<uint64_t>(kStage, le - c0);
     __syncthreads();
     stage_chunk(sm, av, cam, c0, n);
     __syncthreads();
-    if (valid) {
-      for (int e = 0; e < n; ++e) {
-        float a[3], b[3];
-        int jlo = 0, jhi = 0;
-        if (pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi) && w < out1) {
-          pid[w] = sm.id[e];
-          if (mode == 0) {
-            pa[w] = make_float4(a[0], a[1], a[2], __int_as_float(jlo));
-            pb[w] = make_float4(b[0], b[1], b[2], __int_as_float(jhi));
-          }
-          ++w;
+    const uint64_t wc = w;
+    uint32_t word = 0;
+    for (int e = 0; e < n; ++e) {
+      float a[3], b[3];
+      int jlo = 0, jhi = 0;
+      const bool hit = valid && pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi) && w < out1;
+      if (hit) {
+        if (mode == 0) {
+          tpa[w] = make_float4(a[0], a[1], a[2], __int_as_float(sm.id[e]));
+          tpb[w] = make_float4(b[0], b[1], b[2], __int_as_float((int)ray));
+          tpj[w] = make_int2(jlo, jhi);
+        } else {
+          ids[w] = sm.id[e];
         }
+        ++w;
+        word |= 1u << (e & 31);
+      }
+      if ((e & 31) == 31 || e == n - 1) {
+        s_bits[e >> 5][threadIdx.x] = word;
+        word = 0;
+      }
+    }
+    if (mode != 0) continue;
+    // per-entry lists of pair indices: wave counts, then positions
+    for (int e = 0; e < n; ++e) {
+      const bool bit = (s_bits[e >> 5][threadIdx.x] >> (e & 31)) & 1u;
+      const unsigned long long m = __ballot(bit);
+      if (lane == 0) s_cnt[wave][e] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    uint64_t pidx = wc;
+    for (int e = 0; e < n; ++e) {
+      const bool bit = (s_bits[e >> 5][threadIdx.x] >> (e & 31)) & 1u;
+      const unsigned long long m = __ballot(bit);
+      if (bit) {
+        uint32_t base = 0;
+        for (int q = 0; q < wave; ++q) base += s_cnt[q][e];
+        const uint64_t pos = av.entry_off[c0 + e] + base + (uint32_t)__popcll(m & lt);
+        entry_pairs[pos] = (uint32_t)pidx;
+        ++pidx;
       }
     }
   }
-  if (valid) sort_segment(pa, pb, pid, out0, w - out0, mode);
+  if (mode != 0 || !valid) return;
+  // rank the ray's pairs by (jlo, list position), 8 at a time, and move them
+  const int n = (int)(w - out0);
+  for (int i0 = 0; i0 < n; i0 += 8) {
+    int key[8], rank[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      key[q] = i0 + q < n ? tpj[out0 + i0 + q].x : INT_MAX;
+      rank[q] = 0;
+    }
+    for (int j = 0; j < n; ++j) {
+      const int kj = tpj[out0 + j].x;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) rank[q] += (kj < key[q] || (kj == key[q] && j < i0 + q)) ? 1 : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (i0 + q < n) {
+        const uint64_t src = out0 + i0 + q, dst = out0 + rank[q];
+        pa[dst] = tpa[src];
+        pb[dst] = tpb[src];
+        pj[dst] = tpj[src];
+        perm[src] = (uint32_t)dst;
+      }
+    }
+  }
 }
 
-hipError_t launch_hit_emit(const AccelView &av, int mode, float4 *pa, float4 *pb, int32_t *pid,
-                           hipStream_t s) {
+__global__ __launch_bounds__(256) void k_remap_pairs(uint32_t *__restrict__ entry_pairs,
+                                                     const uint32_t *__restrict__ perm, uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) entry_pairs[i] = perm[entry_pairs[i]];
+}
+
+hipError_t launch_hit_emit(const AccelView &av, int mode, float4 *tpa, float4 *tpb, int2 *tpj, float4 *pa,
+                           float4 *pb, int2 *pj, uint32_t *perm, uint32_t *entry_pairs, int32_t *ids,
+                           uint64_t n_pairs, hipStream_t s) {
   const int ntile = av.V * av.tiles_x * av.tiles_y;
   if (ntile == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hit_emit, dim3(ntile), dim3(kTileThreads), 0, s, av, mode, pa, pb, pid);
+  hipLaunchKernelGGL(k_hit_emit, dim3(ntile), dim3(kTileThreads), 0, s, av, mode, tpa, tpb, tpj, pa, pb, pj, perm,
+                     entry_pairs, ids);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || mode != 0 || n_pairs == 0) return e;
+  hipLaunchKernelGGL(k_remap_pairs, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s, entry_pairs, perm, n_pairs);
   return hipGetLastError();
 }
 

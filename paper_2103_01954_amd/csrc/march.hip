@@ -10,20 +10,26 @@
 // and the march stops once T > 1 - eps_early.
 //
 // Backward: the additive rule makes every sample's contribution independent
-// of the others except through the clamp, so the backward replays each ray
-// from its stored final state (last sample j_end and, if clamped, T before the
-// clamp) without any per-sample storage:
+// of the others except through the clamp, so the backward replays each
+// (ray, primitive) pair from the ray's stored final state (last sample j_end
+// and, if clamped, T before the clamp) without any per-sample storage:
 //   Tdot = dL/dA (unclamped)  or  -g . C_S / sigma_S (clamped at sample S)
 //   dL/dsigma_kj = dt (Tdot + g . c_kj),   dL/dc_kj = dt sigma_kj g      (j < S)
-//   dL/dsigma_kS = (1 - T_{S-1}) g . (c_kS - C_S/sigma_S) / sigma_S
+//   dL/dsigma_kS = (1 - T_{S-1}) (g . c_kS + Tdot) / sigma_S
 //   dL/dc_kS     = (1 - T_{S-1}) (sigma_kS / sigma_S) g
-// Channel adjoints go to the 8 payload corners with the trilinear weights
-// (atomics, accumulated in registers while consecutive samples stay in one
-// voxel cell) and to the pose through y = A (o + t d - pos).
+// The pairs are replayed one workgroup per (screen tile, primitive): channel
+// adjoints go to the 8 voxel corners with the trilinear weights, accumulated
+// in registers while consecutive samples stay in one cell and then in an LDS
+// copy of the primitive's gradient, which is added to device memory once per
+// workgroup; the pose gradient (through y = A (o + t d - pos)) is reduced over
+// the workgroup.
 //
 // Built with -ffp-contract=off; fused multiply-adds are written explicitly.
 #include <hip/hip_runtime.h>
 #include <stdlib.h>
+
+#include <algorithm>
+#include <climits>
 
 #include "internal.h"
 
@@ -157,6 +163,8 @@ __device__ __forceinline__ void load_corners(const void *pay, size_t b0, int M, 
   v[7] = Voxels<BF16>::load(pay, b0 + MM + M + 1);
 }
 
+__device__ __forceinline__ int prim_of(const float4 &A) { return __float_as_int(A.w); }
+
 // Accumulated state of one ray.
 struct RayState {
   float T = 0.f, I0 = 0.f, I1 = 0.f, I2 = 0.f, t_prev = -1.0f;
@@ -186,58 +194,22 @@ __device__ __forceinline__ bool composite(RayState &st, int j, float sig, float 
   return true;
 }
 
-// Sample by sample: at each sample, every open pair of the ray is evaluated.
-template <bool BF16>
-__device__ void march_ray_samples(const AccelView &av, const void *pay, uint64_t beg, uint64_t end, RayState &st) {
-  const float dt = av.step, lim = 1.0f - av.eps;
-  const int M = av.M;
-  const float hM = 0.5f * (float)(M - 1);
-  const size_t M3 = (size_t)M * M * M;
-  uint64_t base = beg, nxt = beg;
-  int j = jlo_of(av.pa[beg]);
-  while (true) {
-    // open every pair whose interval has started; drop finished ones in front
-    while (nxt < end && jlo_of(av.pa[nxt]) <= j) ++nxt;
-    while (base < nxt && jhi_of(av.pb[base]) < j) ++base;
-    if (base == nxt) {
-      if (nxt == end) break;
-      j = jlo_of(av.pa[nxt]);   // skip empty space to the next pair
-      continue;
-    }
-    const float tau = (float)j * dt;
-    float sig = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-    for (uint64_t e = base; e < nxt; ++e) {
-      const float4 B = av.pb[e];
-      if (jhi_of(B) < j) continue;
-      const float4 A = av.pa[e];
-      const Cell c = locate(A, B, tau, M, hM);
-      const float4 s = trilinear<BF16>(pay, (size_t)av.pid[e] * M3 + c.idx, M, c);
-      sig += s.w;
-      c0 = fmaf(s.w, s.x, c0);
-      c1 = fmaf(s.w, s.y, c1);
-      c2 = fmaf(s.w, s.z, c2);
-      ++st.n_prim;
-    }
-    ++st.n_ray;
-    if (composite(st, j, sig, c0, c1, c2, dt, lim)) break;
-    ++j;
-  }
-}
-
-// Window by window: the samples J..J+kWin-1 of a ray are gathered pair by pair
-// into per-sample sums held in registers (the voxel corners of a pair stay in
-// registers while consecutive samples remain in one cell), then composited in
-// sample order.  Same sums in the same order as sample by sample.
+// The samples J..J+kWin-1 of a ray are gathered pair by pair into per-sample
+// sums held in registers (a pair's 8 voxel corners stay in registers while
+// consecutive samples remain in one cell), then composited in sample order.
+// The ray's pairs are sorted by (first sample, primitive id): a window visits
+// only the pairs that overlap it, and the primitives of one sample are summed
+// in primitive-id order.
 constexpr int kWin = 8;
 
 template <bool BF16>
-__device__ void march_ray_windows(const AccelView &av, const void *pay, uint64_t beg, uint64_t end, RayState &st) {
+__device__ void march_ray(const AccelView &av, const void *pay, uint64_t beg, uint64_t end, RayState &st) {
   const float dt = av.step, lim = 1.0f - av.eps;
   const int M = av.M;
   const float hM = 0.5f * (float)(M - 1);
   const size_t M3 = (size_t)M * M * M;
-  uint64_t e0 = beg;
-  int J = jlo_of(av.pa[beg]);
+  uint64_t e0 = beg;           // pairs before e0 have ended before the window
+  int J = av.pj[beg].x;
   while (true) {
     float as[kWin], ar[kWin], ag[kWin], ab[kWin];
     int cnt[kWin];
@@ -246,15 +218,15 @@ __device__ void march_ray_windows(const AccelView &av, const void *pay, uint64_t
       as[w] = ar[w] = ag[w] = ab[w] = 0.f;
       cnt[w] = 0;
     }
+    const int J1 = J + kWin;
     for (uint64_t e = e0; e < end; ++e) {
+      const int2 r = av.pj[e];
+      if (r.x >= J1) break;
+      if (r.y < J) continue;
+      const int lo = max(r.x, J) - J, hi = min(r.y, J1 - 1) - J;
       const float4 A = av.pa[e];
-      const int jl = jlo_of(A);
-      if (jl >= J + kWin) break;
       const float4 B = av.pb[e];
-      const int jh = jhi_of(B);
-      if (jh < J) continue;
-      const int lo = max(jl, J) - J, hi = min(jh, J + kWin - 1) - J;
-      const size_t kb = (size_t)av.pid[e] * M3;
+      const size_t kb = (size_t)prim_of(A) * M3;
       int cur = -1;
       float4 v[8];
 #pragma unroll
@@ -285,31 +257,27 @@ __device__ void march_ray_windows(const AccelView &av, const void *pay, uint64_t
       }
     }
     if (stop) break;
-    J += kWin;
-    // the next occupied sample: pairs in front of e0 have all ended before J,
-    // and every later pair starts no earlier than e0
-    while (e0 < end && jhi_of(av.pb[e0]) < J) ++e0;
+    // next occupied sample: every pair in front of e0 ends before J1, and all
+    // later pairs start no earlier than e0 does
+    while (e0 < end && av.pj[e0].y < J1) ++e0;
     if (e0 == end) break;
-    J = max(J, jlo_of(av.pa[e0]));
+    J = max(J1, av.pj[e0].x);
   }
 }
 
-template <bool BF16, bool WINDOWS>
+template <bool BF16>
 __global__ __launch_bounds__(kTileThreads) void k_march_fwd(AccelView av, const void *__restrict__ pay,
                                                              float4 *__restrict__ rgba,
                                                              mvp_ray_aux *__restrict__ aux,
                                                              unsigned long long *__restrict__ counters) {
   __shared__ int s_list[kTileThreads];
   __shared__ int s_wave[kTileThreads / kWave];
-  const int T = av.tiles_x * av.tiles_y;
   const int tile = blockIdx.x;
-  const int v = tile / T, tt = tile % T;
-  const int tx0 = (tt % av.tiles_x) * kTile, ty0 = (tt / av.tiles_x) * kTile;
-
+  int total;
   {
-    const int px = tx0 + (threadIdx.x % kTile), py = ty0 + (threadIdx.x / kTile);
-    const bool valid = px < av.W && py < av.H;
-    const size_t ray = ((size_t)v * av.H + py) * av.W + px;
+    size_t ray;
+    int v, px, py;
+    const bool valid = tile_ray(av, tile, threadIdx.x, &ray, &v, &px, &py);
     bool act = false;
     if (valid) {
       act = av.ray_off[ray + 1] > av.ray_off[ray];
@@ -318,22 +286,14 @@ __global__ __launch_bounds__(kTileThreads) void k_march_fwd(AccelView av, const 
         if (aux) aux[ray] = mvp_ray_aux{-1, -1.0f};
       }
     }
-    compact_tile(act, s_list, s_wave);
+    total = compact_tile(act, s_list, s_wave);
   }
-  int total = 0;
-#pragma unroll
-  for (int w = 0; w < kTileThreads / kWave; ++w) total += s_wave[w];
-
   RayState st;
   if ((int)threadIdx.x < total) {
-    const int lp = s_list[threadIdx.x];
-    const int px = tx0 + (lp % kTile), py = ty0 + (lp / kTile);
-    const size_t ray = ((size_t)v * av.H + py) * av.W + px;
-    const uint64_t beg = av.ray_off[ray], end = av.ray_off[ray + 1];
-    if (WINDOWS)
-      march_ray_windows<BF16>(av, pay, beg, end, st);
-    else
-      march_ray_samples<BF16>(av, pay, beg, end, st);
+    size_t ray;
+    int v, px, py;
+    tile_ray(av, tile, s_list[threadIdx.x], &ray, &v, &px, &py);
+    march_ray<BF16>(av, pay, av.ray_off[ray], av.ray_off[ray + 1], st);
     rgba[ray] = make_float4(st.I0, st.I1, st.I2, st.T);
     if (aux) aux[ray] = mvp_ray_aux{st.j_end, st.t_prev};
   }
@@ -347,34 +307,16 @@ __global__ __launch_bounds__(kTileThreads) void k_march_fwd(AccelView av, const 
   }
 }
 
-static bool fwd_windows() {
-  static const bool w = [] {
-    const char *e = getenv("MVP_FWD_IMPL");
-    return !(e && e[0] == 's');
-  }();
-  return w;
-}
-
 hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, float *rgba, mvp_ray_aux *aux,
                             unsigned long long *counters, hipStream_t s) {
   const int ntile = av.V * av.tiles_x * av.tiles_y;
   if (ntile == 0) return hipSuccess;
-  const bool win = fwd_windows();
-  if (p.payload_dtype == MVP_BF16) {
-    if (win)
-      hipLaunchKernelGGL((k_march_fwd<true, true>), dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
-                         (float4 *)rgba, aux, counters);
-    else
-      hipLaunchKernelGGL((k_march_fwd<true, false>), dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
-                         (float4 *)rgba, aux, counters);
-  } else {
-    if (win)
-      hipLaunchKernelGGL((k_march_fwd<false, true>), dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
-                         (float4 *)rgba, aux, counters);
-    else
-      hipLaunchKernelGGL((k_march_fwd<false, false>), dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
-                         (float4 *)rgba, aux, counters);
-  }
+  if (p.payload_dtype == MVP_BF16)
+    hipLaunchKernelGGL(k_march_fwd<true>, dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
+                       (float4 *)rgba, aux, counters);
+  else
+    hipLaunchKernelGGL(k_march_fwd<false>, dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
+                       (float4 *)rgba, aux, counters);
   return hipGetLastError();
 }
 
@@ -382,236 +324,294 @@ hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, float *rgba
 // backward
 // ---------------------------------------------------------------------------
 
-struct BwdOut {
-  float *pay, *pos, *rot, *scale;
-};
-
-__device__ __forceinline__ void flush_cell(float *g_pay, size_t base, int M, const float (&acc)[8][4]) {
-  const size_t MM = (size_t)M * M;
-  const size_t off[8] = {0, 1, (size_t)M, (size_t)M + 1, MM, MM + 1, MM + M, MM + M + 1};
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    float *dst = g_pay + (base + off[c]) * 4;
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) unsafeAtomicAdd(dst + ch, acc[c][ch]);
-  }
-}
-
+// Per-ray constants of the adjoint: (Tdot, (1 - T_{S-1}) / sigma_S).  Tdot is
+// dL/dA for an unclamped ray and -g . C_S/sigma_S for a ray clamped at its
+// last sample S (recomputed here from the pairs open at S).
 template <bool BF16>
-__global__ __launch_bounds__(kTileThreads) void k_march_bwd(AccelView av, const float *__restrict__ pos,
-                                                             const float *__restrict__ rot,
-                                                             const float *__restrict__ scale,
-                                                             const void *__restrict__ pay,
-                                                             const mvp_ray_aux *__restrict__ aux,
-                                                             const float4 *__restrict__ grad_rgba,
-                                                             BwdOut out) {
-  __shared__ int s_list[kTileThreads];
-  __shared__ int s_wave[kTileThreads / kWave];
-  const int T = av.tiles_x * av.tiles_y;
-  const int tile = blockIdx.x;
-  const int v = tile / T, tt = tile % T;
-  const int tx0 = (tt % av.tiles_x) * kTile, ty0 = (tt / av.tiles_x) * kTile;
-  {
-    const int px = tx0 + (threadIdx.x % kTile), py = ty0 + (threadIdx.x / kTile);
-    bool act = false;
-    if (px < av.W && py < av.H) {
-      const size_t ray = ((size_t)v * av.H + py) * av.W + px;
-      const float4 g = grad_rgba[ray];
-      act = aux[ray].j_end >= 0 && (g.x != 0.f || g.y != 0.f || g.z != 0.f || g.w != 0.f);
-    }
-    compact_tile(act, s_list, s_wave);
-  }
-  int total = 0;
-#pragma unroll
-  for (int w = 0; w < kTileThreads / kWave; ++w) total += s_wave[w];
-  if ((int)threadIdx.x >= total) return;
-
-  const int lp = s_list[threadIdx.x];
-  const int px = tx0 + (lp % kTile), py = ty0 + (lp / kTile);
-  const size_t ray = ((size_t)v * av.H + py) * av.W + px;
-  const uint64_t beg = av.ray_off[ray], end = av.ray_off[ray + 1];
-  const float4 g = grad_rgba[ray];
-  const mvp_ray_aux ax = aux[ray];
-  const int j_end = ax.j_end;
-  const bool clamped = ax.t_prev >= 0.f;
-  const float dt = av.step;
-  const int M = av.M;
-  const float hM = 0.5f * (float)(M - 1);
-  const size_t M3 = (size_t)M * M * M;
-
-  // per-ray constants of the adjoint
-  float tdot = g.w, w_s = 0.f, sig_s = 1.f, cb0 = 0.f, cb1 = 0.f, cb2 = 0.f;
-  if (clamped) {
-    const float tau = (float)j_end * dt;
+__global__ __launch_bounds__(256) void k_bwd_rays(AccelView av, const void *__restrict__ pay,
+                                                  const mvp_ray_aux *__restrict__ aux,
+                                                  const float4 *__restrict__ grad_rgba,
+                                                  float2 *__restrict__ rc, size_t R) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const mvp_ray_aux ax = aux[r];
+  const float4 g = grad_rgba[r];
+  float tdot = g.w, wsig = 0.f;
+  if (ax.j_end >= 0 && ax.t_prev >= 0.f) {
+    const int M = av.M;
+    const float hM = 0.5f * (float)(M - 1);
+    const size_t M3 = (size_t)M * M * M;
+    const float tau = (float)ax.j_end * av.step;
     float sig = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-    for (uint64_t e = beg; e < end; ++e) {
+    for (uint64_t e = av.ray_off[r]; e < av.ray_off[r + 1]; ++e) {
+      const int2 jr = av.pj[e];
+      if (jr.x > ax.j_end) break;          // sorted by first sample
+      if (jr.y < ax.j_end) continue;
       const float4 A = av.pa[e];
-      if (jlo_of(A) > j_end) break;
       const float4 B = av.pb[e];
-      if (jhi_of(B) < j_end) continue;
       const Cell c = locate(A, B, tau, M, hM);
-      const float4 s = trilinear<BF16>(pay, (size_t)av.pid[e] * M3 + c.idx, M, c);
+      float4 v[8];
+      load_corners<BF16>(pay, (size_t)prim_of(A) * M3 + c.idx, M, v);
+      const float4 s = trilerp(v, c);
       sig += s.w;
       c0 = fmaf(s.w, s.x, c0);
       c1 = fmaf(s.w, s.y, c1);
       c2 = fmaf(s.w, s.z, c2);
     }
-    sig_s = sig;
-    cb0 = c0 / sig;
-    cb1 = c1 / sig;
-    cb2 = c2 / sig;
-    tdot = -(g.x * cb0 + g.y * cb1 + g.z * cb2);
-    w_s = 1.0f - ax.t_prev;
+    tdot = -(g.x * (c0 / sig) + g.y * (c1 / sig) + g.z * (c2 / sig));
+    wsig = (1.0f - ax.t_prev) / sig;
   }
+  rc[r] = make_float2(tdot, wsig);
+}
 
-  // ray direction for the pose chain (unit, through the pixel centre)
-  const DevCam &cam = av.cams[v];
-  float d[3];
-  {
-    const float u = (float)px + 0.5f, w = (float)py + 0.5f;
-    float e[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) e[i] = cam.P[3 * i] * u + cam.P[3 * i + 1] * w + cam.P[3 * i + 2];
-    const float inv = 1.0f / sqrtf(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) d[i] = e[i] * inv;
-  }
+struct BwdOut {
+  float *pay, *pos, *rot, *scale;
+};
 
+// Add the 32 register-accumulated corner gradients of one cell: into the LDS
+// copy of the primitive's gradient (LDS_ACC) or straight into device memory.
+template <bool LDS_ACC>
+__device__ __forceinline__ void flush_cell(float *dst, size_t cell, int M, const float (&acc)[8][4]) {
   const size_t MM = (size_t)M * M;
-  for (uint64_t e = beg; e < end; ++e) {
-    const float4 A = av.pa[e];
-    const int jl = jlo_of(A);
-    if (jl > j_end) break;
-    const float4 B = av.pb[e];
-    const int jh = min(jhi_of(B), j_end);
-    if (jh < jl) continue;
-    const int k = av.pid[e];
-    const size_t kb = (size_t)k * M3;
-    float G0 = 0.f, G1 = 0.f, G2 = 0.f, H0 = 0.f, H1 = 0.f, H2 = 0.f;
-    int cur = -1;
-    float4 cv[8];
-    float acc[8][4];
-    for (int j = jl; j <= jh; ++j) {
-      const float tau = (float)j * dt;
-      const Cell c = locate(A, B, tau, M, hM);
-      if (c.idx != cur) {
-        if (cur >= 0 && out.pay) flush_cell(out.pay, kb + cur, M, acc);
-        const size_t b0 = kb + c.idx;
-        cv[0] = Voxels<BF16>::load(pay, b0);
-        cv[1] = Voxels<BF16>::load(pay, b0 + 1);
-        cv[2] = Voxels<BF16>::load(pay, b0 + M);
-        cv[3] = Voxels<BF16>::load(pay, b0 + M + 1);
-        cv[4] = Voxels<BF16>::load(pay, b0 + MM);
-        cv[5] = Voxels<BF16>::load(pay, b0 + MM + 1);
-        cv[6] = Voxels<BF16>::load(pay, b0 + MM + M);
-        cv[7] = Voxels<BF16>::load(pay, b0 + MM + M + 1);
+  const size_t off[8] = {0, 1, (size_t)M, (size_t)M + 1, MM, MM + 1, MM + M, MM + M + 1};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
-        cur = c.idx;
-      }
-      const float fx = c.f[0], fy = c.f[1], fz = c.f[2];
-      const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
-      float w[8];
+  for (int q = 0; q < 8; ++q) {
+    float *p = dst + (cell + off[q]) * 4;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) w[q] = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
-      float r = 0.f, gg = 0.f, b = 0.f, s = 0.f;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        r = fmaf(w[q], cv[q].x, r);
-        gg = fmaf(w[q], cv[q].y, gg);
-        b = fmaf(w[q], cv[q].z, b);
-        s = fmaf(w[q], cv[q].w, s);
-      }
-      float a0, a1, a2, a3;   // dL/d(r, g, b, sigma) of this prim-sample
-      if (clamped && j == j_end) {
-        const float gd = g.x * (r - cb0) + g.y * (gg - cb1) + g.z * (b - cb2);
-        a3 = w_s * gd / sig_s;
-        const float ws = w_s * s / sig_s;
-        a0 = ws * g.x;
-        a1 = ws * g.y;
-        a2 = ws * g.z;
-      } else {
-        a3 = dt * (tdot + g.x * r + g.y * gg + g.z * b);
-        const float ws = dt * s;
-        a0 = ws * g.x;
-        a1 = ws * g.y;
-        a2 = ws * g.z;
-      }
-      float sc[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        acc[q][0] = fmaf(w[q], a0, acc[q][0]);
-        acc[q][1] = fmaf(w[q], a1, acc[q][1]);
-        acc[q][2] = fmaf(w[q], a2, acc[q][2]);
-        acc[q][3] = fmaf(w[q], a3, acc[q][3]);
-        sc[q] = a0 * cv[q].x + a1 * cv[q].y + a2 * cv[q].z + a3 * cv[q].w;
-      }
-      // gradient of the trilinear interpolant of sc with respect to y
-      const float gx = hM * (wy[0] * wz[0] * (sc[1] - sc[0]) + wy[1] * wz[0] * (sc[3] - sc[2]) +
-                             wy[0] * wz[1] * (sc[5] - sc[4]) + wy[1] * wz[1] * (sc[7] - sc[6]));
-      const float gyv = hM * (wx[0] * wz[0] * (sc[2] - sc[0]) + wx[1] * wz[0] * (sc[3] - sc[1]) +
-                              wx[0] * wz[1] * (sc[6] - sc[4]) + wx[1] * wz[1] * (sc[7] - sc[5]));
-      const float gz = hM * (wx[0] * wy[0] * (sc[4] - sc[0]) + wx[1] * wy[0] * (sc[5] - sc[1]) +
-                             wx[0] * wy[1] * (sc[6] - sc[2]) + wx[1] * wy[1] * (sc[7] - sc[3]));
-      G0 += gx;
-      G1 += gyv;
-      G2 += gz;
-      H0 = fmaf(tau, gx, H0);
-      H1 = fmaf(tau, gyv, H1);
-      H2 = fmaf(tau, gz, H2);
+    for (int ch = 0; ch < 4; ++ch) {
+      if (LDS_ACC)
+        atomicAdd(p + ch, acc[q][ch]);
+      else
+        unsafeAtomicAdd(p + ch, acc[q][ch]);
     }
-    if (cur >= 0 && out.pay) flush_cell(out.pay, kb + cur, M, acc);
+  }
+}
 
-    // pose: y = A (o + tau d - t), A = diag(1/s) R^T
-    if (out.pos || out.rot || out.scale) {
-      const float G[3] = {G0, G1, G2}, H[3] = {H0, H1, H2};
-      float Am[9], t[3];
+// Backward, one workgroup per culling-list entry (tile, primitive k): the
+// tile's rays that form a pair with k replay their samples inside k.  The
+// payload gradient of k is accumulated in LDS (LDS_ACC) and added to device
+// memory once per workgroup; the pose gradient is reduced over the workgroup
+// and added with 15 atomics.
+template <bool BF16, bool LDS_ACC>
+__global__ __launch_bounds__(kTileThreads) void k_bwd_entries(AccelView av, const float *__restrict__ rot,
+                                                               const float *__restrict__ scale,
+                                                               const void *__restrict__ pay,
+                                                               const mvp_ray_aux *__restrict__ aux,
+                                                               const float4 *__restrict__ grad_rgba,
+                                                               const float2 *__restrict__ rc,
+                                                               int64_t n_entries, BwdOut out) {
+  extern __shared__ float s_grad[];
+  __shared__ float s_pose[kTileThreads / kWave][16];
+  const int M = av.M;
+  const float hM = 0.5f * (float)(M - 1);
+  const size_t M3 = (size_t)M * M * M;
+  const size_t MM = (size_t)M * M;
+  const int nacc = (int)(M3 * 4);
+  const float dt = av.step;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const bool pose = out.pos || out.rot || out.scale;
+
+  for (int64_t gi = blockIdx.x; gi < n_entries; gi += gridDim.x) {
+    const uint64_t e0 = av.entry_off[gi], e1 = av.entry_off[gi + 1];
+    if (e1 == e0) continue;                              // uniform over the workgroup
+    const int k = (int)av.tile_list[gi];
+    if (LDS_ACC && out.pay) {
+      for (int i = threadIdx.x; i < nacc; i += kTileThreads) s_grad[i] = 0.f;
+      __syncthreads();
+    }
+    float P[15];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const float4 row = av.xf[3 * (size_t)k + i];
-        Am[3 * i] = row.x; Am[3 * i + 1] = row.y; Am[3 * i + 2] = row.z; t[i] = row.w;
-      }
-      const float p[3] = {cam.o[0] - t[0], cam.o[1] - t[1], cam.o[2] - t[2]};
-      if (out.pos) {
+    for (int i = 0; i < 15; ++i) P[i] = 0.f;
+    if (threadIdx.x < e1 - e0) {
+      const uint32_t e = av.entry_pairs[e0 + threadIdx.x];
+      const float4 A = av.pa[e];
+      const float4 B = av.pb[e];
+      const int2 jr = av.pj[e];
+      const int ray = __float_as_int(B.w);
+      const mvp_ray_aux ax = aux[ray];
+      const float4 g = grad_rgba[ray];
+      const float2 c2 = rc[ray];
+      const float tdot = c2.x, wsig = c2.y;
+      const bool clamped = ax.t_prev >= 0.f;
+      const int jh = min(jr.y, ax.j_end);
+      const size_t kb = (size_t)k * M3;
+      float *gdst = out.pay ? (LDS_ACC ? s_grad : out.pay + kb * 4) : nullptr;
+      float G0 = 0.f, G1 = 0.f, G2 = 0.f, H0 = 0.f, H1 = 0.f, H2 = 0.f;
+      int cur = -1;
+      float4 cv[8];
+      float acc[8][4];
+      for (int j = jr.x; j <= jh; ++j) {
+        const float tau = (float)j * dt;
+        const Cell c = locate(A, B, tau, M, hM);
+        if (c.idx != cur) {
+          if (cur >= 0 && gdst) flush_cell<LDS_ACC>(gdst, cur, M, acc);
+          load_corners<BF16>(pay, kb + c.idx, M, cv);
 #pragma unroll
-        for (int m = 0; m < 3; ++m)
-          unsafeAtomicAdd(out.pos + 3 * (size_t)k + m, -(Am[m] * G[0] + Am[3 + m] * G[1] + Am[6 + m] * G[2]));
+          for (int q = 0; q < 8; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
+          cur = c.idx;
+        }
+        const float fx = c.f[0], fy = c.f[1], fz = c.f[2];
+        const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
+        float w[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w[q] = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
+        float r = 0.f, gg = 0.f, b = 0.f, s = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          r = fmaf(w[q], cv[q].x, r);
+          gg = fmaf(w[q], cv[q].y, gg);
+          b = fmaf(w[q], cv[q].z, b);
+          s = fmaf(w[q], cv[q].w, s);
+        }
+        const float gc = g.x * r + g.y * gg + g.z * b;
+        float a3, ws;   // dL/dsigma and the factor of g in dL/d(rgb) for this prim-sample
+        if (clamped && j == ax.j_end) {
+          a3 = wsig * (gc + tdot);
+          ws = wsig * s;
+        } else {
+          a3 = dt * (tdot + gc);
+          ws = dt * s;
+        }
+        const float a0 = ws * g.x, a1 = ws * g.y, a2 = ws * g.z;
+        float sc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          acc[q][0] = fmaf(w[q], a0, acc[q][0]);
+          acc[q][1] = fmaf(w[q], a1, acc[q][1]);
+          acc[q][2] = fmaf(w[q], a2, acc[q][2]);
+          acc[q][3] = fmaf(w[q], a3, acc[q][3]);
+          sc[q] = a0 * cv[q].x + a1 * cv[q].y + a2 * cv[q].z + a3 * cv[q].w;
+        }
+        // gradient of the trilinear interpolant of sc with respect to y
+        const float gx = hM * (wy[0] * wz[0] * (sc[1] - sc[0]) + wy[1] * wz[0] * (sc[3] - sc[2]) +
+                               wy[0] * wz[1] * (sc[5] - sc[4]) + wy[1] * wz[1] * (sc[7] - sc[6]));
+        const float gyv = hM * (wx[0] * wz[0] * (sc[2] - sc[0]) + wx[1] * wz[0] * (sc[3] - sc[1]) +
+                                wx[0] * wz[1] * (sc[6] - sc[4]) + wx[1] * wz[1] * (sc[7] - sc[5]));
+        const float gz = hM * (wx[0] * wy[0] * (sc[4] - sc[0]) + wx[1] * wy[0] * (sc[5] - sc[1]) +
+                               wx[0] * wy[1] * (sc[6] - sc[2]) + wx[1] * wy[1] * (sc[7] - sc[3]));
+        G0 += gx;
+        G1 += gyv;
+        G2 += gz;
+        H0 = fmaf(tau, gx, H0);
+        H1 = fmaf(tau, gyv, H1);
+        H2 = fmaf(tau, gz, H2);
       }
-      if (out.rot || out.scale) {
-        float Rm[9], s[3];
+      if (cur >= 0 && gdst) flush_cell<LDS_ACC>(gdst, cur, M, acc);
+
+      if (pose) {
+        // y = A (o + tau d - t), A = diag(1/s) R^T; d is the unit pixel ray
+        int rv, px, py;
+        slot_pixel(av, (size_t)ray, &rv, &px, &py);
+        const DevCam &cam = av.cams[rv];
+        const float u = (float)px + 0.5f, wv = (float)py + 0.5f;
+        float d[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) d[i] = cam.P[3 * i] * u + cam.P[3 * i + 1] * wv + cam.P[3 * i + 2];
+        const float inv = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) d[i] *= inv;
+        const float G[3] = {G0, G1, G2}, H[3] = {H0, H1, H2};
+        float Am[9], t[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const float4 row = av.xf[3 * (size_t)k + i];
+          Am[3 * i] = row.x; Am[3 * i + 1] = row.y; Am[3 * i + 2] = row.z; t[i] = row.w;
+        }
+        const float p[3] = {cam.o[0] - t[0], cam.o[1] - t[1], cam.o[2] - t[2]};
+        float Rm[9], sk[3];
 #pragma unroll
         for (int i = 0; i < 9; ++i) Rm[i] = rot[9 * (size_t)k + i];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) s[i] = scale[3 * (size_t)k + i];
+        for (int i = 0; i < 3; ++i) sk[i] = scale[3 * (size_t)k + i];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) P[m] = -(Am[m] * G[0] + Am[3 + m] * G[1] + Am[6 + m] * G[2]);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
           float rp = 0.f;
 #pragma unroll
           for (int m = 0; m < 3; ++m) {
-            const float P = fmaf(p[m], G[i], d[m] * H[i]);
-            if (out.rot) unsafeAtomicAdd(out.rot + 9 * (size_t)k + 3 * m + i, P / s[i]);
-            rp = fmaf(Rm[3 * m + i], P, rp);
+            const float Pm = fmaf(p[m], G[i], d[m] * H[i]);
+            P[3 + 3 * m + i] = Pm / sk[i];
+            rp = fmaf(Rm[3 * m + i], Pm, rp);
           }
-          if (out.scale) unsafeAtomicAdd(out.scale + 3 * (size_t)k + i, -rp / (s[i] * s[i]));
+          P[12 + i] = -rp / (sk[i] * sk[i]);
         }
       }
     }
+    if (pose) {
+#pragma unroll
+      for (int i = 0; i < 15; ++i) {
+        float x = P[i];
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+        if (lane == 0) s_pose[wave][i] = x;
+      }
+    }
+    __syncthreads();
+    if (pose && threadIdx.x < 15) {
+      float x = 0.f;
+#pragma unroll
+      for (int w = 0; w < kTileThreads / kWave; ++w) x += s_pose[w][threadIdx.x];
+      const int i = threadIdx.x;
+      if (i < 3) {
+        if (out.pos) unsafeAtomicAdd(out.pos + 3 * (size_t)k + i, x);
+      } else if (i < 12) {
+        if (out.rot) unsafeAtomicAdd(out.rot + 9 * (size_t)k + (i - 3), x);
+      } else {
+        if (out.scale) unsafeAtomicAdd(out.scale + 3 * (size_t)k + (i - 12), x);
+      }
+    }
+    if (LDS_ACC && out.pay) {
+      float *dst = out.pay + M3 * 4 * (size_t)k;
+      for (int i = threadIdx.x; i < nacc; i += kTileThreads) {
+        const float x = s_grad[i];
+        if (x != 0.f) unsafeAtomicAdd(dst + i, x);
+      }
+    }
+    __syncthreads();   // LDS is reused by the next entry
   }
-  (void)pos;
+  (void)MM;
 }
 
-hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, const mvp_ray_aux *aux,
-                            const float *grad_rgba, float *g_pay, float *g_pos, float *g_rot,
-                            float *g_scale, hipStream_t s) {
-  const int ntile = av.V * av.tiles_x * av.tiles_y;
-  if (ntile == 0 || p.n_prim == 0) return hipSuccess;
-  BwdOut out{g_pay, g_pos, g_rot, g_scale};
-  if (p.payload_dtype == MVP_BF16)
-    hipLaunchKernelGGL(k_march_bwd<true>, dim3(ntile), dim3(kTileThreads), 0, s, av, p.pos, p.rot, p.scale,
-                       p.payload, aux, (const float4 *)grad_rgba, out);
+// Largest per-primitive gradient (M^3 x 4 floats) accumulated in LDS.
+constexpr size_t kLdsGradBytes = 64 * 1024;
+
+hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_entries,
+                            const mvp_ray_aux *aux, const float *grad_rgba, float2 *rc, float *g_pay,
+                            float *g_pos, float *g_rot, float *g_scale, hipStream_t s) {
+  const size_t R = (size_t)av.n_slots;
+  if (R == 0 || p.n_prim == 0 || n_entries == 0) return hipSuccess;
+  const bool bf16 = p.payload_dtype == MVP_BF16;
+  const unsigned rb = (unsigned)((R + 255) / 256);
+  if (bf16)
+    hipLaunchKernelGGL(k_bwd_rays<true>, dim3(rb), dim3(256), 0, s, av, p.payload, aux, (const float4 *)grad_rgba, rc, R);
   else
-    hipLaunchKernelGGL(k_march_bwd<false>, dim3(ntile), dim3(kTileThreads), 0, s, av, p.pos, p.rot, p.scale,
-                       p.payload, aux, (const float4 *)grad_rgba, out);
+    hipLaunchKernelGGL(k_bwd_rays<false>, dim3(rb), dim3(256), 0, s, av, p.payload, aux, (const float4 *)grad_rgba, rc, R);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t M3 = (size_t)p.M * p.M * p.M;
+  const size_t lds = M3 * 16;
+  bool in_lds = lds <= kLdsGradBytes;
+  if (in_lds && g_pay) {
+    // allow more than the default dynamic LDS per workgroup (gfx950 has 160 KB)
+    const void *fn = bf16 ? (const void *)k_bwd_entries<true, true> : (const void *)k_bwd_entries<false, true>;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsGradBytes) != hipSuccess) {
+      (void)hipGetLastError();
+      in_lds = lds <= 48 * 1024;
+    }
+  }
+  const unsigned grid = (unsigned)std::min<int64_t>(n_entries, 1 << 20);
+  BwdOut out{g_pay, g_pos, g_rot, g_scale};
+  const size_t shm = in_lds && g_pay ? lds : 0;
+#define MVP_BWD(B, L)                                                                                   \
+  hipLaunchKernelGGL((k_bwd_entries<B, L>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale, \
+                     p.payload, aux, (const float4 *)grad_rgba, (const float2 *)rc, n_entries, out)
+  if (bf16) {
+    if (in_lds) MVP_BWD(true, true); else MVP_BWD(true, false);
+  } else {
+    if (in_lds) MVP_BWD(false, true); else MVP_BWD(false, false);
+  }
+#undef MVP_BWD
   return hipGetLastError();
 }
 

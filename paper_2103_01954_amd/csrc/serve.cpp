@@ -183,7 +183,7 @@ void Server::start_locked(Slot &slot, uint64_t t, std::unique_lock<std::mutex> &
   lk.unlock();
   Admit admit{&Server::admit_cb, this};
   mvp_accel *a = nullptr;
-  mvp_status st = build_accel(ctx_, &prims, &req.cam, 1, &req.params, &a, slot.stream, &admit);
+  mvp_status st = build_accel(ctx_, &prims, &req.cam, 1, &req.params, nullptr, 0, &a, slot.stream, &admit);
   if (st == MVP_OK) {
     slot.accel = a;
     hipError_t e = launch_zero_u64((uint64_t *)a->counters, 2, slot.stream);

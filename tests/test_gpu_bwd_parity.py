@@ -151,3 +151,20 @@ def test_autograd_function_matches_direct_backward(mvp_ctx):
         e = rel_l2(leaf.grad.cpu().numpy(), direct[key].cpu().numpy())
         assert e <= 1e-5, key
     acc.destroy()
+
+
+@pytest.mark.parametrize("m", [16, 20], ids=["M16-lds", "M20-global"])
+def test_large_grid_gradients(mvp_ctx, m):
+    """M=16 accumulates a primitive's gradient in 64 KiB of LDS; M=20 exceeds it
+    and accumulates in device memory."""
+    prims = scenes.random_box_scene(91, n=5, m=m, s_lo=0.3, s_hi=0.6)
+    cam = scenes.look_at_camera(np.random.default_rng(92), 40, 40)
+    params = scenes.MarchParams(1 / 256, 1e-4)
+    say(f"M={m} gradients")
+    ref_fwd = oracle.render(prims, cam, params)
+    up = _upstream(ref_fwd["rgba"].shape, 93, ref_fwd["margin"])
+    _, ref = oracle.render_grad(prims, cam, params, up)
+    acc, dp, rgba, aux = gpu_forward(mvp_ctx, prims, [cam], params)
+    gpu = _gpu_grads(acc, dp, aux, up.reshape(1, cam.height, cam.width, 4))
+    _check(gpu, ref, 1e-4)
+    acc.destroy()
