@@ -19,6 +19,13 @@ and at S:
 Samples after the stop contribute nothing.  The early-stop decision and box
 membership are piecewise constant and carry no gradient.
 
+Sequential variant: if primitive k* clamps at sample S with T* the opacity
+just before it, then I gains c_k*S (1 - T*) and A = 1, so
+    Tdot = -g . c_k*S,
+every sample before S and every primitive before k* at S take the regular
+formulas above, dL/dc_k*S = (1 - T*) g, dL/dsigma_k*S = 0, and the
+primitives after k* at S contribute nothing.
+
 The channel adjoints flow to the 8 payload corners through the trilinear
 weights, and to the pose through the local coordinate
 y = A (x - t), A = diag(1/s) R^T, x = o + tau d:
@@ -29,7 +36,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .render import fade_window, render
+from .render import combine_mode, fade_window, render
 
 F64 = np.float64
 
@@ -70,29 +77,39 @@ def render_grad(prims, cam, params, grad_rgba, pixels=None, geometry="fp32", bac
     dt = float(params.step)
 
     # per-ray constants
+    seq = combine_mode(params) == "sequential"
+    ray = tr["ray"]
+    val = tr["val"]
+    c, sig = val[:, :3], val[:, 3]
     sat = out["t_prev"] >= 0
     tdot = gr[:, 3].copy()
     cbar = np.zeros((R, 3))
     sig_s = np.ones(R)
     for r in np.nonzero(sat)[0]:
         s = last_group[r]
-        sig_s[r] = g_sig[s]
-        cbar[r] = g_col[s] / g_sig[s]
-        tdot[r] = -float(gr[r, :3] @ cbar[r])
+        if seq:
+            i = np.nonzero((tr["group"] == s) & (tr["prim"] == out["k_star"][r]))[0][0]
+            tdot[r] = -float(gr[r, :3] @ c[i])
+        else:
+            sig_s[r] = g_sig[s]
+            cbar[r] = g_col[s] / g_sig[s]
+            tdot[r] = -float(gr[r, :3] @ cbar[r])
 
-    ray = tr["ray"]
     g = gr[ray, :3]
-    val = tr["val"]
-    c, sig = val[:, :3], val[:, 3]
     used = tr["group"] <= last_group[ray]
     at_s = sat[ray] & (tr["group"] == last_group[ray])
+    if seq:   # before the clamping primitive: regular steps
+        at_s &= tr["prim"] >= out["k_star"][ray]
     regular = used & ~at_s
 
     adj = np.zeros((ntr, 4))
     gc_dot = np.einsum("ij,ij->i", g, c)
     adj[regular, 3] = dt * (tdot[ray][regular] + gc_dot[regular])
     adj[regular, :3] = dt * sig[regular, None] * g[regular]
-    if np.any(at_s):
+    if seq:
+        clamp = at_s & (tr["prim"] == out["k_star"][ray])
+        adj[clamp, :3] = (1.0 - out["t_star"][ray][clamp])[:, None] * g[clamp]
+    elif np.any(at_s):
         w = (1.0 - out["t_prev"][ray][at_s])
         ss = sig_s[ray][at_s]
         adj[at_s, 3] = w * np.einsum("ij,ij->i", g[at_s], c[at_s] - cbar[ray][at_s]) / ss

@@ -26,9 +26,18 @@ What is computed, following the paper:
   colour/opacity field of Sec. 3.2.2.  This is what accumulating the
   primitives one after another gives up to the saturation point, and it does
   not depend on the order of the primitive list.
+* Variant (``params.combine == "sequential"``): the primitives containing a
+  sample are accumulated one after another in increasing primitive id, each
+  with its own clamp step, as when the primitives are visited in a fixed
+  traversal order instead of being merged into one field (Sec. 3.2.2 notes
+  that both readings coincide up to saturation).  A sample whose summed step
+  does not saturate gives exactly the sum rule; at the saturating sample the
+  primitives before the clamping one k* add sigma_k c_k dt, k* adds
+  c_k* (1 - T) and later ones nothing.
 * Outputs per ray: I (premultiplied colour, the integral as written), A, the
   index of the last sample processed and, if the clamp was hit there, the
-  value of T before it.
+  value of T before it (and, for the sequential variant, the clamping
+  primitive and T just before it).
 
 Values are FP64: the local coordinate of a sample is y = a + tau b evaluated in
 FP64 from the canonical FP32 local ray (a, b) of ``geometry.py`` (or from an
@@ -222,6 +231,53 @@ def accumulate(sig, col, dt, eps):
     return np.array(I), T, last, t_prev, margin
 
 
+def accumulate_sequential(sig, col, prim, bounds, dt, eps):
+    """The sequential variant of ``accumulate``: per-primitive clamp steps in
+    increasing primitive id within each sample.
+
+    sig[n], col[n,3]: opacity density and colour (not opacity-weighted) of
+    every (sample, primitive) of one ray, ordered by (sample, primitive id);
+    prim[n] the primitive ids; bounds[g]..bounds[g+1] the entries of sample
+    group g.  Returns I, T, index of the last group processed, T before the
+    clamping group (-1 if none), margin, the clamping primitive (-1 if none)
+    and T just before it."""
+    T = 0.0
+    I = [0.0, 0.0, 0.0]
+    last, t_prev, k_star, t_star = -1, -1.0, -1, -1.0
+    margin = np.inf
+    sig = sig.tolist()
+    col = col.tolist()
+    for g in range(len(bounds) - 1):
+        b0, b1 = int(bounds[g]), int(bounds[g + 1])
+        last = g
+        margin = min(margin, abs(T + sum(sig[b0:b1]) * dt - 1.0))
+        t_group = T
+        for i in range(b0, b1):
+            s, c = sig[i], col[i]
+            step_t = s * dt
+            margin = min(margin, abs(T + step_t - 1.0))
+            if T + step_t <= 1.0:
+                T += step_t
+                I = [I[0] + s * c[0] * dt, I[1] + s * c[1] * dt, I[2] + s * c[2] * dt]
+            else:
+                u = 1.0 - T
+                I = [I[0] + c[0] * u, I[1] + c[1] * u, I[2] + c[2] * u]
+                t_prev, k_star, t_star, T = t_group, int(prim[i]), T, 1.0
+                return np.array(I), T, last, t_prev, margin, k_star, t_star
+        if eps > 0:
+            margin = min(margin, abs(T - (1.0 - eps)))
+        if T > 1.0 - eps:
+            break
+    return np.array(I), T, last, t_prev, margin, k_star, t_star
+
+
+def combine_mode(params):
+    mode = getattr(params, "combine", "sum") or "sum"
+    if mode not in ("sum", "sequential"):
+        raise ValueError(f"unknown combine rule {mode!r}")
+    return mode
+
+
 def fade_window(M, alpha, beta):
     """Opacity fade window of Sec. 3.1.3 at the voxel centres,
     W(x, y, z) = exp(-alpha (|x|^beta + |y|^beta + |z|^beta)) with (x, y, z) the
@@ -261,7 +317,10 @@ def render(prims, cam, params, pixels=None, geometry="fp32", _want_grad=False, b
       ray_samples   [R]          samples inside >= 1 hit primitive, up to the stop
       prim_samples  [R]          (sample, primitive) pairs up to the stop
       margin        [R]          closest distance of a clamp/stop decision to its threshold
+      k_star        [R]          clamping primitive of the sequential variant, or -1
+      t_star        [R]          T just before k_star (sequential variant), or -1
     """
+    seq = combine_mode(params) == "sequential"
     d, A, tr, g_sig, g_col, rb = _samples(windowed(prims, params), cam, params, pixels, geometry, _want_grad)
     R = d.shape[0]
     rgba = np.zeros((R, 4))
@@ -270,13 +329,23 @@ def render(prims, cam, params, pixels=None, geometry="fp32", _want_grad=False, b
     ray_samples = np.zeros(R, dtype=np.int64)
     last_group = np.full(R, -1, dtype=np.int64)
     margin = np.full(R, np.inf)
-    gj = tr["j"][np.searchsorted(tr["group"], np.arange(g_sig.size))] if g_sig.size else np.zeros(0)
+    k_star = np.full(R, -1, dtype=np.int64)
+    t_star = np.full(R, -1.0)
+    gfirst = np.searchsorted(tr["group"], np.arange(g_sig.size + 1))   # entries of each group
+    gj = tr["j"][gfirst[:-1]] if g_sig.size else np.zeros(0)
     for r in range(R):
         g0, g1 = rb[r], rb[r + 1]
         if g0 == g1:
             continue
-        I, T, last, tp, mg = accumulate(g_sig[g0:g1], g_col[g0:g1], float(params.step),
-                                        float(params.eps_early))
+        if seq:
+            e0, e1 = gfirst[g0], gfirst[g1]
+            I, T, last, tp, mg, ks, ts = accumulate_sequential(
+                tr["val"][e0:e1, 3], tr["val"][e0:e1, :3], tr["prim"][e0:e1], gfirst[g0:g1 + 1] - e0,
+                float(params.step), float(params.eps_early))
+            k_star[r], t_star[r] = ks, ts
+        else:
+            I, T, last, tp, mg = accumulate(g_sig[g0:g1], g_col[g0:g1], float(params.step),
+                                            float(params.eps_early))
         rgba[r, :3] = I
         rgba[r, 3] = T
         j_end[r] = gj[g0 + last]
@@ -287,7 +356,7 @@ def render(prims, cam, params, pixels=None, geometry="fp32", _want_grad=False, b
     in_use = tr["group"] <= last_group[tr["ray"]] if tr["ray"].size else np.zeros(0, dtype=bool)
     prim_samples = np.bincount(tr["ray"][in_use], minlength=R) if R else np.zeros(0, dtype=np.int64)
     out = {"rgba": rgba, "j_end": j_end, "t_prev": t_prev, "ray_samples": ray_samples,
-           "prim_samples": prim_samples, "margin": margin, "dirs": d}
+           "prim_samples": prim_samples, "margin": margin, "k_star": k_star, "t_star": t_star, "dirs": d}
     if background is not None:
         out["rgba_premultiplied"] = rgba
         out["rgba"] = composite_background(rgba, background)

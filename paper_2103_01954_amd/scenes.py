@@ -66,6 +66,9 @@ class MarchParams:
     step: float
     eps_early: float
     t_near: float = 0.0
+    fade_alpha: float = 0.0     # opacity fade window (0: off; the paper uses 8)
+    fade_beta: float = 8.0
+    combine: str = "sum"        # "sum" (global field) or "sequential" (primitive-id order)
 
 
 @dataclass
