@@ -85,11 +85,29 @@ typedef struct {
 
 /* March parameters: sample j sits at t = j * step (step > 0); the march stops
  * after a sample once the accumulated opacity exceeds 1 - eps_early
- * (0 <= eps_early < 1, Sec. 3.2.2); only t >= t_near >= 0 is integrated. */
+ * (0 <= eps_early < 1, Sec. 3.2.2); only t >= t_near >= 0 is integrated.
+ * fade_alpha > 0 multiplies every voxel's opacity by the fade window of
+ * Sec. 3.1.3, W = exp(-fade_alpha (|x|^b + |y|^b + |z|^b)), b = fade_beta > 0,
+ * (x, y, z) the voxel's normalised coordinates in [-1,1]^3 (the paper uses
+ * alpha = beta = 8); gradients are then with respect to the stored payload.
+ * fade_alpha = 0 disables it.
+ * combine chooses how the primitives containing one sample are merged
+ * (Sec. 3.2.2): MVP_COMBINE_SUM adds their opacities and opacity-weighted
+ * colours into one global field sample before the clamp step;
+ * MVP_COMBINE_SEQUENTIAL takes them one after another in increasing primitive
+ * id, each with its own clamp step, as a fixed traversal order would.  The two
+ * agree on every sample that does not saturate; at the saturating sample the
+ * sequential rule gives the clamp to the first primitive that crosses 1.  Any
+ * other value is MVP_ERR_INVALID. */
+typedef enum { MVP_COMBINE_SUM = 0, MVP_COMBINE_SEQUENTIAL = 1 } mvp_combine;
+
 typedef struct {
   float step;
   float eps_early;
   float t_near;
+  float fade_alpha;
+  float fade_beta;
+  int32_t combine;         /* mvp_combine */
 } mvp_march_params;
 
 /* Per-ray state the forward leaves for the backward: the index of the last
@@ -139,8 +157,9 @@ mvp_status mvp_build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camer
  * keeps a copy); a pixel may appear more than once as long as no 16x16 tile
  * receives more than 256 rays.  Forward and backward then read and write
  * per-ray arrays in the order of `rays`: rgba [n_rays,4], aux [n_rays],
- * grad_rgba [n_rays,4].  Out-of-range ids fail with MVP_ERR_INVALID.  BLOCKS
- * like mvp_build_accel. */
+ * grad_rgba [n_rays,4].  Out-of-range ids fail with MVP_ERR_INVALID.  rays may
+ * be NULL only when n_rays == 0 (an empty subset).  BLOCKS like
+ * mvp_build_accel. */
 mvp_status mvp_build_accel_rays(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams,
                                 int32_t n_views, const mvp_march_params *params, const int64_t *rays,
                                 int64_t n_rays, mvp_accel **out, void *stream);
@@ -169,6 +188,20 @@ mvp_status mvp_render_bwd(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims 
                           float *grad_payload, float *grad_pos, float *grad_rot,
                           float *grad_scale, void *stream);
 
+/* The same forward composited over a background (the alpha compositing of
+ * Sec. 3.1.4 with the premultiplied colour): rgba = (I + (1 - A) B, A) with
+ * background B [rays,3] float32 (rays ordered like rgba). */
+mvp_status mvp_render_fwd_bg(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims *prims,
+                             const float *background, float *rgba, mvp_ray_aux *aux, void *stream);
+
+/* Backward of mvp_render_fwd_bg: needs its background and output rgba (for
+ * A); additionally ACCUMULATES dL/dB = (1 - A) dL/dcolour into
+ * grad_background [rays,3] (may be NULL). */
+mvp_status mvp_render_bwd_bg(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims *prims,
+                             const float *background, const float *rgba, const mvp_ray_aux *aux,
+                             const float *grad_rgba, float *grad_payload, float *grad_pos,
+                             float *grad_rot, float *grad_scale, float *grad_background, void *stream);
+
 /* Sample counts of the most recent forward on this structure (BLOCKS on
  * `stream`): ray-samples (samples inside >= 1 intersected primitive, up to the
  * early stop) and prim-samples ((sample, primitive) pairs, i.e. trilinear
@@ -184,6 +217,20 @@ mvp_status mvp_accel_counts(mvp_ctx *ctx, const mvp_accel *accel, uint64_t *ray_
 mvp_status mvp_debug_hits(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims *prims,
                           int64_t *offsets, int32_t *ids, int64_t ids_cap, int64_t *n_total,
                           void *stream);
+
+/* Kernel timing for benchmarks: from mvp_timing_start on, every forward
+ * (MVP_KERNEL_FWD_MARCH: the forward march kernel) and backward
+ * (MVP_KERNEL_BWD_MARCH: the per-pair backward kernel, without the per-ray
+ * constants kernel before it) records a pair of HIP events around that kernel
+ * on the stream it is launched on, for the first `capacity` launches of each.
+ * mvp_timing_read BLOCKS until the recorded launches have finished and writes
+ * their durations in milliseconds to the HOST array ms [capacity], launch
+ * order, and their number to *n.  mvp_timing_stop ends recording and frees
+ * the events.  Requests of the serving scheduler are not recorded. */
+typedef enum { MVP_KERNEL_FWD_MARCH = 0, MVP_KERNEL_BWD_MARCH = 1 } mvp_kernel;
+mvp_status mvp_timing_start(mvp_ctx *ctx, int32_t capacity);
+mvp_status mvp_timing_read(mvp_ctx *ctx, int32_t kernel, float *ms, int32_t *n);
+mvp_status mvp_timing_stop(mvp_ctx *ctx);
 
 /* ---- serving: resident scenes and continuous batching ----------------------- */
 

@@ -24,13 +24,18 @@ class mvp_prims(C.Structure):
                 ("scale", C.c_void_p), ("payload", C.c_void_p)]
 
 
+MVP_COMBINE_SUM, MVP_COMBINE_SEQUENTIAL = 0, 1
+MVP_KERNEL_FWD_MARCH, MVP_KERNEL_BWD_MARCH = 0, 1
+
+
 class mvp_camera(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("origin", C.c_float * 3),
                 ("pix2dir", C.c_float * 9)]
 
 
 class mvp_march_params(C.Structure):
-    _fields_ = [("step", C.c_float), ("eps_early", C.c_float), ("t_near", C.c_float)]
+    _fields_ = [("step", C.c_float), ("eps_early", C.c_float), ("t_near", C.c_float),
+                ("fade_alpha", C.c_float), ("fade_beta", C.c_float), ("combine", C.c_int32)]
 
 
 class mvp_ray_aux(C.Structure):
@@ -63,8 +68,13 @@ _SIGS = {
     "mvp_accel_get_info": ([P, C.POINTER(mvp_accel_info)], C.c_int),
     "mvp_render_fwd": ([P, P, C.POINTER(mvp_prims), P, P, P], C.c_int),
     "mvp_render_bwd": ([P, P, C.POINTER(mvp_prims), P, P, P, P, P, P, P], C.c_int),
+    "mvp_render_fwd_bg": ([P, P, C.POINTER(mvp_prims), P, P, P, P], C.c_int),
+    "mvp_render_bwd_bg": ([P, P, C.POINTER(mvp_prims), P, P, P, P, P, P, P, P, P, P], C.c_int),
     "mvp_accel_counts": ([P, P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), P], C.c_int),
     "mvp_debug_hits": ([P, P, C.POINTER(mvp_prims), P, P, C.c_int64, C.POINTER(C.c_int64), P], C.c_int),
+    "mvp_timing_start": ([P, C.c_int32], C.c_int),
+    "mvp_timing_read": ([P, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_int32)], C.c_int),
+    "mvp_timing_stop": ([P], C.c_int),
     "mvp_serve_configure": ([P, C.c_size_t, C.c_int32], C.c_int),
     "mvp_scene_create": ([P, C.POINTER(mvp_prims), C.POINTER(C.c_uint64)], C.c_int),
     "mvp_scene_release": ([P, C.c_uint64], C.c_int),

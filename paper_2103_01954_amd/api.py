@@ -75,8 +75,16 @@ def c_camera(cam: Camera) -> L.mvp_camera:
     return c
 
 
+_COMBINE = {"sum": L.MVP_COMBINE_SUM, "sequential": L.MVP_COMBINE_SEQUENTIAL}
+
+
 def c_params(p: MarchParams) -> L.mvp_march_params:
-    return L.mvp_march_params(float(p.step), float(p.eps_early), float(p.t_near))
+    combine = getattr(p, "combine", "sum") or "sum"
+    if combine not in _COMBINE:
+        raise ValueError(f"combine must be one of {sorted(_COMBINE)}, got {combine!r}")
+    return L.mvp_march_params(float(p.step), float(p.eps_early), float(p.t_near),
+                              float(getattr(p, "fade_alpha", 0.0)), float(getattr(p, "fade_beta", 8.0)),
+                              _COMBINE[combine])
 
 
 class Context:
@@ -93,6 +101,23 @@ class Context:
         if self.handle:
             L.check("mvp_destroy", self.lib.mvp_destroy(self.handle))
             self.handle = None
+
+    def timing_start(self, capacity: int):
+        """Record HIP events around the forward and backward march kernels of the
+        next `capacity` launches of each (mvp_timing_start)."""
+        L.check("mvp_timing_start", self.lib.mvp_timing_start(self.handle, int(capacity)))
+        self._timing_cap = int(capacity)
+
+    def timing_read(self, kernel: str):
+        """Durations in ms of the recorded launches of kernel "fwd" or "bwd" (blocks)."""
+        kind = {"fwd": L.MVP_KERNEL_FWD_MARCH, "bwd": L.MVP_KERNEL_BWD_MARCH}[kernel]
+        buf = (C.c_float * self._timing_cap)()
+        n = C.c_int32()
+        L.check("mvp_timing_read", self.lib.mvp_timing_read(self.handle, kind, buf, C.byref(n)))
+        return [float(buf[i]) for i in range(n.value)]
+
+    def timing_stop(self):
+        L.check("mvp_timing_stop", self.lib.mvp_timing_stop(self.handle))
 
     def build_accel(self, prims: DevicePrims, cams: Sequence[Camera], params: MarchParams,
                     stream=None, rays: Optional[torch.Tensor] = None) -> "Accel":
@@ -147,7 +172,10 @@ class Accel:
             L.check("mvp_accel_destroy", self.ctx.lib.mvp_accel_destroy(self.ctx.handle, h, s))
 
     def render_fwd(self, prims: DevicePrims, rgba: Optional[torch.Tensor] = None,
-                   aux: Optional[torch.Tensor] = None, want_aux: bool = True, stream=None):
+                   aux: Optional[torch.Tensor] = None, want_aux: bool = True, stream=None,
+                   background: Optional[torch.Tensor] = None):
+        """Forward march -> (rgba, aux).  With a background [rays,3] the colour
+        is composited as I + (1 - A) B."""
         shape = self.ray_shape
         dev = prims.pos.device
         if rgba is None:
@@ -155,25 +183,43 @@ class Accel:
         if aux is None and want_aux:
             aux = torch.empty(shape, dtype=torch.int64, device=dev)   # 8-byte mvp_ray_aux per ray
         cp = prims.c_struct()
-        L.check("mvp_render_fwd", self.ctx.lib.mvp_render_fwd(
-            self.ctx.handle, self.handle, C.byref(cp), rgba.data_ptr(),
-            aux.data_ptr() if aux is not None else None, _stream(stream)))
+        aux_p = aux.data_ptr() if aux is not None else None
+        if background is None:
+            L.check("mvp_render_fwd", self.ctx.lib.mvp_render_fwd(
+                self.ctx.handle, self.handle, C.byref(cp), rgba.data_ptr(), aux_p, _stream(stream)))
+        else:
+            bg = _check_bg(background, shape)
+            L.check("mvp_render_fwd_bg", self.ctx.lib.mvp_render_fwd_bg(
+                self.ctx.handle, self.handle, C.byref(cp), bg.data_ptr(), rgba.data_ptr(), aux_p, _stream(stream)))
         return rgba, aux
 
     def render_bwd(self, prims: DevicePrims, aux: torch.Tensor, grad_rgba: torch.Tensor,
-                   grads: Optional[dict] = None, stream=None) -> dict:
-        """Accumulate gradients into ``grads`` (allocated as zeros if None)."""
+                   grads: Optional[dict] = None, stream=None, background: Optional[torch.Tensor] = None,
+                   rgba: Optional[torch.Tensor] = None) -> dict:
+        """Accumulate gradients into ``grads`` (allocated as zeros if None).  For
+        a composited forward pass its background and rgba; grads then also
+        gets "background"."""
         dev = prims.pos.device
         if grads is None:
             grads = {"payload": torch.zeros(prims.payload.shape, dtype=torch.float32, device=dev),
                      "pos": torch.zeros_like(prims.pos), "rot": torch.zeros_like(prims.rot),
                      "scale": torch.zeros_like(prims.scale)}
+            if background is not None:
+                grads["background"] = torch.zeros(self.ray_shape + (3,), dtype=torch.float32, device=dev)
         g = grad_rgba.contiguous()
         cp = prims.c_struct()
         ptr = lambda k: grads[k].data_ptr() if grads.get(k) is not None else None
-        L.check("mvp_render_bwd", self.ctx.lib.mvp_render_bwd(
-            self.ctx.handle, self.handle, C.byref(cp), aux.data_ptr(), g.data_ptr(),
-            ptr("payload"), ptr("pos"), ptr("rot"), ptr("scale"), _stream(stream)))
+        if background is None:
+            L.check("mvp_render_bwd", self.ctx.lib.mvp_render_bwd(
+                self.ctx.handle, self.handle, C.byref(cp), aux.data_ptr(), g.data_ptr(),
+                ptr("payload"), ptr("pos"), ptr("rot"), ptr("scale"), _stream(stream)))
+        else:
+            bg = _check_bg(background, self.ray_shape)
+            assert rgba is not None, "the composited backward needs the forward's rgba"
+            L.check("mvp_render_bwd_bg", self.ctx.lib.mvp_render_bwd_bg(
+                self.ctx.handle, self.handle, C.byref(cp), bg.data_ptr(), rgba.contiguous().data_ptr(),
+                aux.data_ptr(), g.data_ptr(), ptr("payload"), ptr("pos"), ptr("rot"), ptr("scale"),
+                ptr("background"), _stream(stream)))
         return grads
 
     def counts(self, stream=None):
@@ -200,6 +246,12 @@ class Accel:
                                                               off.data_ptr(), ids.data_ptr(), cap,
                                                               C.byref(total), _stream(stream)))
         return off.cpu().numpy(), ids[:total.value].cpu().numpy()
+
+
+def _check_bg(bg: torch.Tensor, shape) -> torch.Tensor:
+    if bg.dtype != torch.float32 or not bg.is_cuda or tuple(bg.shape) != tuple(shape) + (3,):
+        raise ValueError(f"background must be a float32 CUDA tensor of shape {tuple(shape) + (3,)}")
+    return bg.contiguous()
 
 
 def aux_fields(aux: torch.Tensor):

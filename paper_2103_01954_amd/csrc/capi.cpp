@@ -2,6 +2,7 @@
 // backward marches, and the test exports.  Serving lives in serve.cpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -180,6 +181,9 @@ mvp_status check_params(const mvp_march_params *p) {
   if (!(p->step > 0.0f) || !std::isfinite(p->step)) { set_error("step must be finite and > 0"); return MVP_ERR_INVALID; }
   if (!(p->eps_early >= 0.0f && p->eps_early < 1.0f)) { set_error("eps_early must be in [0,1)"); return MVP_ERR_INVALID; }
   if (!(p->t_near >= 0.0f) || !std::isfinite(p->t_near)) { set_error("t_near must be finite and >= 0"); return MVP_ERR_INVALID; }
+  if (!(p->fade_alpha >= 0.0f) || !std::isfinite(p->fade_alpha)) { set_error("fade_alpha must be finite and >= 0"); return MVP_ERR_INVALID; }
+  if (p->fade_alpha > 0.0f && (!(p->fade_beta > 0.0f) || !std::isfinite(p->fade_beta))) { set_error("fade_beta must be finite and > 0"); return MVP_ERR_INVALID; }
+  if (p->combine != MVP_COMBINE_SUM && p->combine != MVP_COMBINE_SEQUENTIAL) { set_error("combine must be MVP_COMBINE_SUM or MVP_COMBINE_SEQUENTIAL"); return MVP_ERR_INVALID; }
   return MVP_OK;
 }
 
@@ -287,7 +291,7 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   int4 *rect = nullptr;
   uint32_t *tile_cnt = nullptr, *ray_cnt = nullptr, *entry_cnt = nullptr;
   uint8_t *scratch = nullptr, *scratch2 = nullptr;
-  const size_t sb = scan_scratch_bytes(ntile > R ? ntile : R);
+  const size_t sb = scan_scratch_bytes(std::max<size_t>(std::max<size_t>(ntile, R), (size_t)N));
   if (admit) {
     const size_t base = n_views * sizeof(DevCam) + 3 * (size_t)N * 16 + (ntile + 1) * 8 + (R + 1) * 8 + 16 +
                         (size_t)n_views * N * 16 + ntile * 4 + R * 4 + sb + 9 * 256 +
@@ -337,16 +341,30 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   if (flag_h & 2u) { set_error("more than 256 rays in one 16x16 tile (repeated pixel ids)"); return MVP_ERR_INVALID; }
   const size_t ntp = n_tile_pairs ? n_tile_pairs : 1;
   const size_t sb2 = scan_scratch_bytes(n_tile_pairs);
-  if (admit) MVP_CHECK(admit->fn(admit->user, ntp * 20 + 8 + sb2 + 4 * 256));
+  if (admit) MVP_CHECK(admit->fn(admit->user, ntp * 20 + 8 + sb2 + (size_t)N * 20 + 24 + 8 * 256));
   MVP_CHECK(keep.get(&a->tile_list, ntp));
-  MVP_CHECK(keep.get(&a->entry_tile, ntp));
   MVP_CHECK(keep.get(&a->entry_off, ntp + 1));
+  MVP_CHECK(keep.get(&a->prim_entries, ntp));
+  MVP_CHECK(keep.get(&a->prim_entry_off, (size_t)N + 1));
+  MVP_CHECK(keep.get(&a->item_off, (size_t)N + 1));
+  uint32_t *prim_cnt = nullptr;
+  MVP_CHECK(temp.get(&prim_cnt, (size_t)N + 1));
   MVP_CHECK(temp.get(&entry_cnt, ntp));
   MVP_CHECK(temp.get(&scratch2, sb2));
   av = a->view(2);
   MVP_HIP(launch_zero_u32(tile_cnt, ntile, s));
-  MVP_HIP(launch_tile_fill(av, rect, tile_cnt, a->tile_list, a->entry_tile, s));
+  MVP_HIP(launch_tile_fill(av, rect, tile_cnt, a->tile_list, s));
   MVP_HIP(launch_segment_sort(a->tile_off, a->tile_list, (int64_t)ntile, s));
+  // transposed lists (primitive -> its entries) and backward work items
+  MVP_HIP(launch_zero_u32(prim_cnt, (size_t)N, s));
+  MVP_HIP(launch_prim_entry_count(a->tile_list, n_tile_pairs, prim_cnt, s));
+  MVP_HIP(launch_scan_u32_u64(prim_cnt, a->prim_entry_off, (size_t)N, scratch, s));
+  MVP_HIP(launch_zero_u32(prim_cnt, (size_t)N, s));
+  MVP_HIP(launch_prim_entry_fill(a->tile_list, n_tile_pairs, a->prim_entry_off, prim_cnt, a->prim_entries, s));
+  MVP_HIP(launch_segment_sort(a->prim_entry_off, a->prim_entries, (int64_t)N, s));
+  MVP_HIP(launch_item_count(a->prim_entry_off, N, backward_item_entries(), prim_cnt, s));
+  MVP_HIP(launch_scan_u32_u64(prim_cnt, a->item_off, (size_t)N, scratch, s));
+  a->n_items_max = (int64_t)(n_tile_pairs / backward_item_entries()) + N;
 
   // per-ray pair counts and per-entry counts, offsets
   MVP_HIP(launch_hit_count(av, 0, ray_cnt, entry_cnt, s));
@@ -356,20 +374,17 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   MVP_CHECK(read_u64(a->ray_off + R, &n_pairs, s));
   if (n_pairs >= (uint64_t)1 << 32) { set_error("%llu ray/primitive pairs exceed 2^32", (unsigned long long)n_pairs); return MVP_ERR_INVALID; }
   const size_t np = n_pairs ? n_pairs : 1;
-  if (admit) MVP_CHECK(admit->fn(admit->user, np * 88 + 8 * 256));
-  float4 *tpa = nullptr, *tpb = nullptr;
-  int2 *tpj = nullptr;
-  uint32_t *perm = nullptr;
+  if (admit) MVP_CHECK(admit->fn(admit->user, np * 52 + 8 * 256));
+  int32_t *tkey = nullptr;
+  uint32_t *trank = nullptr;
   MVP_CHECK(keep.get(&a->pa, np));
   MVP_CHECK(keep.get(&a->pb, np));
   MVP_CHECK(keep.get(&a->pj, np));
   MVP_CHECK(keep.get(&a->entry_pairs, np));
-  MVP_CHECK(temp.get(&tpa, np));
-  MVP_CHECK(temp.get(&tpb, np));
-  MVP_CHECK(temp.get(&tpj, np));
-  MVP_CHECK(temp.get(&perm, np));
+  MVP_CHECK(temp.get(&tkey, np));
+  MVP_CHECK(temp.get(&trank, np));
   av = a->view(2);
-  MVP_HIP(launch_hit_emit(av, 0, tpa, tpb, tpj, a->pa, a->pb, a->pj, perm, a->entry_pairs, nullptr, n_pairs, s));
+  MVP_HIP(launch_hit_emit(av, 0, tkey, trank, a->pa, a->pb, a->pj, a->entry_pairs, nullptr, s));
 
   a->n_tile_pairs = (int64_t)n_tile_pairs;
   a->n_ray_pairs = (int64_t)n_pairs;
@@ -431,6 +446,7 @@ mvp_status mvp_destroy(mvp_ctx *ctx) {
   if (!ctx) { set_error("ctx is NULL"); return MVP_ERR_INVALID; }
   if (ctx->live_accels.load() != 0) { set_error("%d acceleration structures still alive", ctx->live_accels.load()); return MVP_ERR_BUSY; }
   serve_shutdown(ctx);
+  (void)mvp_timing_stop(ctx);
   (void)hipSetDevice(ctx->device);
   delete ctx;
   return MVP_OK;
@@ -444,6 +460,8 @@ mvp_status mvp_build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camer
 mvp_status mvp_build_accel_rays(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams, int32_t n_views,
                                 const mvp_march_params *params, const int64_t *rays, int64_t n_rays,
                                 mvp_accel **out, void *stream) {
+  static const int64_t no_rays = 0;   // an empty list may come as NULL; it is never read
+  if (!rays && n_rays == 0) rays = &no_rays;
   if (!rays) { set_error("rays is NULL"); return MVP_ERR_INVALID; }
   return build_accel(ctx, prims, cams, n_views, params, rays, n_rays, out, (hipStream_t)stream, nullptr);
 }
@@ -459,30 +477,122 @@ mvp_status mvp_accel_get_info(const mvp_accel *a, mvp_accel_info *info) {
   return MVP_OK;
 }
 
-mvp_status mvp_render_fwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims, float *rgba,
-                          mvp_ray_aux *aux, void *stream) {
+// Next free event pair of a kernel kind, or {nullptr, nullptr} when not recording.
+static std::pair<hipEvent_t, hipEvent_t> timer_slot(mvp_ctx *ctx, int kind) {
+  std::lock_guard<std::mutex> g(ctx->timer.m);
+  mvp::KernelTimer &t = ctx->timer;
+  if (t.n[kind] >= t.cap) return {nullptr, nullptr};
+  const int i = t.n[kind]++;
+  return {t.ev[kind][2 * i], t.ev[kind][2 * i + 1]};
+}
+
+static void timer_free(mvp::KernelTimer &t) {
+  for (auto &v : t.ev) {
+    for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    v.clear();
+  }
+  t.cap = 0;
+  t.n[0] = t.n[1] = 0;
+}
+
+mvp_status mvp_timing_start(mvp_ctx *ctx, int32_t capacity) {
+  if (!ctx) { set_error("ctx is NULL"); return MVP_ERR_INVALID; }
+  if (capacity < 1 || capacity > (1 << 16)) { set_error("capacity must be in [1, 65536]"); return MVP_ERR_INVALID; }
+  MVP_HIP(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> g(ctx->timer.m);
+  timer_free(ctx->timer);
+  for (auto &v : ctx->timer.ev) {
+    v.resize(2 * (size_t)capacity, nullptr);
+    for (hipEvent_t &e : v) {
+      if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        timer_free(ctx->timer);
+        set_error("hipEventCreate failed");
+        return MVP_ERR_DEVICE;
+      }
+    }
+  }
+  ctx->timer.cap = capacity;
+  return MVP_OK;
+}
+
+mvp_status mvp_timing_read(mvp_ctx *ctx, int32_t kernel, float *ms, int32_t *n) {
+  if (!ctx || !ms || !n) { set_error("bad argument"); return MVP_ERR_INVALID; }
+  if (kernel != MVP_KERNEL_FWD_MARCH && kernel != MVP_KERNEL_BWD_MARCH) { set_error("unknown kernel %d", kernel); return MVP_ERR_INVALID; }
+  MVP_HIP(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> g(ctx->timer.m);
+  const mvp::KernelTimer &t = ctx->timer;
+  for (int i = 0; i < t.n[kernel]; ++i) {
+    MVP_HIP(hipEventSynchronize(t.ev[kernel][2 * i + 1]));
+    MVP_HIP(hipEventElapsedTime(&ms[i], t.ev[kernel][2 * i], t.ev[kernel][2 * i + 1]));
+  }
+  *n = t.n[kernel];
+  return MVP_OK;
+}
+
+mvp_status mvp_timing_stop(mvp_ctx *ctx) {
+  if (!ctx) { set_error("ctx is NULL"); return MVP_ERR_INVALID; }
+  MVP_HIP(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> g(ctx->timer.m);
+  for (auto &v : ctx->timer.ev)
+    for (hipEvent_t e : v) (void)hipEventSynchronize(e);
+  timer_free(ctx->timer);
+  return MVP_OK;
+}
+
+static mvp_status render_fwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims, const float *bg,
+                             float *rgba, mvp_ray_aux *aux, hipStream_t s) {
   MVP_CHECK(check_render(ctx, a, prims));
   if (!rgba && a->n_slots > 0) { set_error("rgba is NULL"); return MVP_ERR_INVALID; }
-  hipStream_t s = (hipStream_t)stream;
   MVP_HIP(hipSetDevice(ctx->device));
   MVP_HIP(launch_zero_u64((uint64_t *)a->counters, 2, s));
-  MVP_HIP(launch_march_fwd(a->view(prims->M), *prims, rgba, aux, a->counters, s));
+  const auto ev = timer_slot(ctx, MVP_KERNEL_FWD_MARCH);
+  if (ev.first) MVP_HIP(hipEventRecord(ev.first, s));
+  MVP_HIP(launch_march_fwd(a->view(prims->M), *prims, bg, rgba, aux, a->counters, s));
+  if (ev.second) MVP_HIP(hipEventRecord(ev.second, s));
   return MVP_OK;
+}
+
+static mvp_status render_bwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims, const float *bg,
+                             const float *rgba, const mvp_ray_aux *aux, const float *grad_rgba, float *grad_payload,
+                             float *grad_pos, float *grad_rot, float *grad_scale, float *grad_bg, hipStream_t s) {
+  MVP_CHECK(check_render(ctx, a, prims));
+  if ((!aux || !grad_rgba) && a->n_slots > 0) { set_error("aux and grad_rgba are required"); return MVP_ERR_INVALID; }
+  MVP_HIP(hipSetDevice(ctx->device));
+  Blocks temp{ctx, s};
+  mvp::RayConst *rc = nullptr;
+  MVP_CHECK(temp.get(&rc, a->n_rays()));
+  const auto ev = timer_slot(ctx, MVP_KERNEL_BWD_MARCH);
+  MVP_HIP(launch_march_bwd(a->view(prims->M), *prims, a->n_items_max, aux, grad_rgba, bg, rgba, rc, grad_payload,
+                           grad_pos, grad_rot, grad_scale, grad_bg, s, ev.first, ev.second));
+  return MVP_OK;   // the scratch is recycled after the kernels have run
+}
+
+mvp_status mvp_render_fwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims, float *rgba,
+                          mvp_ray_aux *aux, void *stream) {
+  return render_fwd(ctx, a, prims, nullptr, rgba, aux, (hipStream_t)stream);
+}
+
+mvp_status mvp_render_fwd_bg(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims, const float *background,
+                             float *rgba, mvp_ray_aux *aux, void *stream) {
+  if (!background && a && a->n_slots > 0) { set_error("background is NULL"); return MVP_ERR_INVALID; }
+  return render_fwd(ctx, a, prims, background, rgba, aux, (hipStream_t)stream);
 }
 
 mvp_status mvp_render_bwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims, const mvp_ray_aux *aux,
                           const float *grad_rgba, float *grad_payload, float *grad_pos, float *grad_rot,
                           float *grad_scale, void *stream) {
-  MVP_CHECK(check_render(ctx, a, prims));
-  if ((!aux || !grad_rgba) && a->n_slots > 0) { set_error("aux and grad_rgba are required"); return MVP_ERR_INVALID; }
-  hipStream_t s = (hipStream_t)stream;
-  MVP_HIP(hipSetDevice(ctx->device));
-  Blocks temp{ctx, s};
-  float2 *rc = nullptr;
-  MVP_CHECK(temp.get(&rc, a->n_rays()));
-  MVP_HIP(launch_march_bwd(a->view(prims->M), *prims, a->n_tile_pairs, aux, grad_rgba, rc, grad_payload,
-                           grad_pos, grad_rot, grad_scale, s));
-  return MVP_OK;   // the scratch is recycled after the kernels have run
+  return render_bwd(ctx, a, prims, nullptr, nullptr, aux, grad_rgba, grad_payload, grad_pos, grad_rot, grad_scale,
+                    nullptr, (hipStream_t)stream);
+}
+
+mvp_status mvp_render_bwd_bg(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims, const float *background,
+                             const float *rgba, const mvp_ray_aux *aux, const float *grad_rgba, float *grad_payload,
+                             float *grad_pos, float *grad_rot, float *grad_scale, float *grad_background,
+                             void *stream) {
+  if ((!background || !rgba) && a && a->n_slots > 0) { set_error("background and rgba are required"); return MVP_ERR_INVALID; }
+  return render_bwd(ctx, a, prims, background, rgba, aux, grad_rgba, grad_payload, grad_pos, grad_rot, grad_scale,
+                    grad_background, (hipStream_t)stream);
 }
 
 mvp_status mvp_accel_counts(mvp_ctx *ctx, const mvp_accel *a, uint64_t *ray_samples, uint64_t *prim_samples,
@@ -520,7 +630,7 @@ mvp_status mvp_debug_hits(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *pri
   if ((int64_t)total > ids_cap) { set_error("ids_cap %lld < %llu hits", (long long)ids_cap, (unsigned long long)total); return MVP_ERR_OOM; }
   if (total > 0 && !ids) { set_error("ids is NULL"); return MVP_ERR_INVALID; }
   av.ray_off = (const uint64_t *)offsets;
-  MVP_HIP(launch_hit_emit(av, 1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ids, 0, s));
+  MVP_HIP(launch_hit_emit(av, 1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ids, s));
   MVP_HIP(hipStreamSynchronize(s));
   return MVP_OK;
 }

@@ -51,9 +51,20 @@ class Server;  // serving scheduler (serve.cpp)
 
 }  // namespace mvp
 
+namespace mvp {
+// HIP event pairs around the march kernels (benchmark timing).
+struct KernelTimer {
+  std::mutex m;
+  int cap = 0;
+  std::vector<hipEvent_t> ev[2];   // per kernel kind: start/stop of launch i at 2i, 2i+1
+  int n[2] = {0, 0};
+};
+}  // namespace mvp
+
 struct mvp_ctx {
   int device = 0;
   mvp::Arena arena;
+  mvp::KernelTimer timer;
   std::atomic<int> live_accels{0};
   mvp::Server *server = nullptr;
   explicit mvp_ctx(int dev) : device(dev), arena(dev) {}
@@ -68,7 +79,10 @@ struct mvp_accel {
   float4 *xf = nullptr;
   uint64_t *tile_off = nullptr;
   uint32_t *tile_list = nullptr;
-  uint32_t *entry_tile = nullptr;
+  uint64_t *prim_entry_off = nullptr;
+  uint32_t *prim_entries = nullptr;
+  uint64_t *item_off = nullptr;
+  int64_t n_items_max = 0;             // upper bound on the backward work items
   uint64_t *entry_off = nullptr;
   uint32_t *entry_pairs = nullptr;
   uint64_t *ray_off = nullptr;
@@ -87,8 +101,10 @@ struct mvp_accel {
     v.V = V; v.W = W; v.H = H; v.N = N; v.M = M;
     v.tiles_x = tiles_x; v.tiles_y = tiles_y;
     v.step = params.step; v.eps = params.eps_early; v.t_near = params.t_near;
+    v.fade_alpha = params.fade_alpha; v.fade_beta = params.fade_beta; v.combine = params.combine;
     v.cams = cams; v.xf = xf; v.tile_off = tile_off; v.tile_list = tile_list;
-    v.entry_tile = entry_tile; v.entry_off = entry_off; v.entry_pairs = entry_pairs;
+    v.prim_entry_off = prim_entry_off; v.prim_entries = prim_entries; v.item_off = item_off;
+    v.entry_off = entry_off; v.entry_pairs = entry_pairs;
     v.ray_off = ray_off; v.pa = pa; v.pb = pb; v.pj = pj;
     v.n_slots = n_slots; v.ray_pix = ray_pix; v.tile_ray_off = tile_ray_off; v.tile_rays = tile_rays;
     return v;

@@ -349,8 +349,7 @@ hipError_t launch_prep(const mvp_prims &p, const AccelView &av, float4 *xf, int4
 
 __global__ __launch_bounds__(256) void k_tile_fill(AccelView av, const int4 *__restrict__ rect,
                                                    uint32_t *__restrict__ cursor,
-                                                   uint32_t *__restrict__ list,
-                                                   uint32_t *__restrict__ entry_tile) {
+                                                   uint32_t *__restrict__ list) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (size_t)av.V * av.N) return;
   const int v = (int)(i / av.N);
@@ -362,16 +361,63 @@ __global__ __launch_bounds__(256) void k_tile_fill(AccelView av, const int4 *__r
       const size_t tile = (size_t)v * T + (size_t)ty * av.tiles_x + tx;
       const uint32_t slot = atomicAdd(&cursor[tile], 1u);
       list[av.tile_off[tile] + slot] = (uint32_t)k;
-      entry_tile[av.tile_off[tile] + slot] = (uint32_t)tile;
     }
 }
 
 hipError_t launch_tile_fill(const AccelView &av, const int4 *rect, uint32_t *cursor,
-                            uint32_t *tile_list, uint32_t *entry_tile, hipStream_t s) {
+                            uint32_t *tile_list, hipStream_t s) {
   const size_t n = (size_t)av.V * av.N;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, av, rect, cursor,
-                     tile_list, entry_tile);
+                     tile_list);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_prim_entry_count(const uint32_t *__restrict__ list, uint64_t n,
+                                                          uint32_t *__restrict__ cnt) {
+  uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; g < n; g += stride) atomicAdd(&cnt[list[g]], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_prim_entry_fill(const uint32_t *__restrict__ list, uint64_t n,
+                                                         const uint64_t *__restrict__ off,
+                                                         uint32_t *__restrict__ cursor,
+                                                         uint32_t *__restrict__ out) {
+  uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (; g < n; g += stride) {
+    const uint32_t k = list[g];
+    const uint64_t pos = off[k] + atomicAdd(&cursor[k], 1u);
+    if (pos < off[k + 1]) out[pos] = (uint32_t)g;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_item_count(const uint64_t *__restrict__ off, int n, int per_item,
+                                                    uint32_t *__restrict__ cnt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) cnt[k] = (uint32_t)((off[k + 1] - off[k] + per_item - 1) / per_item);
+}
+
+hipError_t launch_prim_entry_count(const uint32_t *tile_list, uint64_t n, uint32_t *cnt, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prim_entry_count, dim3(grid_for(n, 256)), dim3(256), 0, s, tile_list, n, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_prim_entry_fill(const uint32_t *tile_list, uint64_t n, const uint64_t *off, uint32_t *cursor,
+                                  uint32_t *prim_entries, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prim_entry_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, tile_list, n, off, cursor,
+                     prim_entries);
+  return hipGetLastError();
+}
+
+hipError_t launch_item_count(const uint64_t *prim_entry_off, int n_prim, int per_item, uint32_t *cnt,
+                             hipStream_t s) {
+  if (n_prim == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_item_count, dim3((n_prim + 255) / 256), dim3(256), 0, s, prim_entry_off, n_prim, per_item,
+                     cnt);
   return hipGetLastError();
 }
 
@@ -592,132 +638,141 @@ hipError_t launch_hit_count(const AccelView &av, int mode, uint32_t *ray_cnt, ui
   return hipGetLastError();
 }
 
-// Emit kernel.  Each ray writes its pairs in culling-list order (which is
-// primitive-id order) into its segment [ray_off[ray], ray_off[ray+1]) of the
-// temporary arrays tpa/tpb/tpj:
+// Emit kernel, three passes over the tile's culling list (staged in LDS in
+// chunks).  Pass 1 finds the ray's pairs (the slab tests of the count pass,
+// same predicate) and keeps their first samples jlo in list order, which is
+// primitive-id order.  Pass 2 ranks each pair by (jlo, list position), the
+// order the forward marches them in: in LDS for lists of at most kKeys pairs
+// (jlo < 2^24 in the low 24 bits, the rank in the top 8), in device memory
+// (tkey/trank) for longer ones.  Pass 3 repeats the slab tests and writes
+// every pair straight to its ranked slot of the ray's segment
+// [ray_off[ray], ray_off[ray+1]):
 //   pa = (a, primitive id), pb = (b, ray index), pj = (jlo, jhi),
-// and, for every culling-list entry, the (temporary) indices of the pairs
-// formed with it (entry_pairs[entry_off[g] ..]), in pixel order, for the
-// backward's one-workgroup-per-entry reduction.  Then it moves its pairs to
-// pa/pb/pj sorted by (jlo, primitive id), the order the forward marches them
-// in, and records each pair's new index in perm (k_remap_pairs applies it to
-// entry_pairs).  Mode 1 writes only the primitive ids of the slab hits into
-// `ids`, in primitive-id order.
-__global__ __launch_bounds__(kTileThreads) void k_hit_emit(AccelView av, int mode, float4 *__restrict__ tpa,
-                                                            float4 *__restrict__ tpb, int2 *__restrict__ tpj,
-                                                            float4 *__restrict__ pa, float4 *__restrict__ pb,
-                                                            int2 *__restrict__ pj, uint32_t *__restrict__ perm,
+// and lists it under its culling-list entry (entry_pairs[entry_off[g] ..],
+// pixel order) for the backward.  Mode 1 writes only the primitive ids of the
+// slab hits into `ids`, in primitive-id order.
+constexpr int kKeys = 48;
+
+__global__ __launch_bounds__(kTileThreads) void k_hit_emit(AccelView av, int mode, int32_t *__restrict__ tkey,
+                                                            uint32_t *__restrict__ trank, float4 *__restrict__ pa,
+                                                            float4 *__restrict__ pb, int2 *__restrict__ pj,
                                                             uint32_t *__restrict__ entry_pairs,
                                                             int32_t *__restrict__ ids) {
   __shared__ Staged sm;
   __shared__ uint32_t s_bits[kStage / 32][kTileThreads];
   __shared__ uint32_t s_cnt[kTileThreads / kWave][kStage];
+  __shared__ uint32_t s_key[kKeys][kTileThreads];
   const int tile = blockIdx.x;
+  const int t = threadIdx.x;
   int v, px, py;
   size_t ray;
-  const bool valid = tile_ray(av, tile, threadIdx.x, &ray, &v, &px, &py);
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const bool valid = tile_ray(av, tile, t, &ray, &v, &px, &py);
+  const int lane = t & (kWave - 1), wave = t / kWave;
   const DevCam &cam = av.cams[v];
   float d[3];
   pixel_ray(cam, px, py, d);
   const uint64_t out0 = valid ? av.ray_off[ray] : 0;
-  const uint64_t out1 = valid ? av.ray_off[ray + 1] : 0;   // same predicate as the count pass
-  uint64_t w = out0;
+  const int n = valid ? (int)(av.ray_off[ray + 1] - out0) : 0;   // same predicate as the count pass
+  const bool in_lds = n <= kKeys;
   const uint64_t lb = av.tile_off[tile], le = av.tile_off[tile + 1];
   const unsigned long long lt = (1ull << lane) - 1ull;
+  // pass 1: first samples (or, in mode 1, primitive ids) in list order
+  int i = 0;
   for (uint64_t c0 = lb; c0 < le; c0 += kStage) {
-    const int n = (int)min<uint64_t>(kStage, le - c0);
+    const int nc = (int)min<uint64_t>(kStage, le - c0);
     __syncthreads();
-    stage_chunk(sm, av, cam, c0, n);
+    stage_chunk(sm, av, cam, c0, nc);
     __syncthreads();
-    const uint64_t wc = w;
-    uint32_t word = 0;
-    for (int e = 0; e < n; ++e) {
+    for (int e = 0; e < nc; ++e) {
       float a[3], b[3];
       int jlo = 0, jhi = 0;
-      const bool hit = valid && pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi) && w < out1;
-      if (hit) {
-        if (mode == 0) {
-          tpa[w] = make_float4(a[0], a[1], a[2], __int_as_float(sm.id[e]));
-          tpb[w] = make_float4(b[0], b[1], b[2], __int_as_float((int)ray));
-          tpj[w] = make_int2(jlo, jhi);
-        } else {
-          ids[w] = sm.id[e];
-        }
-        ++w;
-        word |= 1u << (e & 31);
-      }
-      if ((e & 31) == 31 || e == n - 1) {
-        s_bits[e >> 5][threadIdx.x] = word;
-        word = 0;
-      }
-    }
-    if (mode != 0) continue;
-    // per-entry lists of pair indices: wave counts, then positions
-    for (int e = 0; e < n; ++e) {
-      const bool bit = (s_bits[e >> 5][threadIdx.x] >> (e & 31)) & 1u;
-      const unsigned long long m = __ballot(bit);
-      if (lane == 0) s_cnt[wave][e] = (uint32_t)__popcll(m);
-    }
-    __syncthreads();
-    uint64_t pidx = wc;
-    for (int e = 0; e < n; ++e) {
-      const bool bit = (s_bits[e >> 5][threadIdx.x] >> (e & 31)) & 1u;
-      const unsigned long long m = __ballot(bit);
-      if (bit) {
-        uint32_t base = 0;
-        for (int q = 0; q < wave; ++q) base += s_cnt[q][e];
-        const uint64_t pos = av.entry_off[c0 + e] + base + (uint32_t)__popcll(m & lt);
-        entry_pairs[pos] = (uint32_t)pidx;
-        ++pidx;
+      if (i < n && pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi)) {
+        if (mode != 0)
+          ids[out0 + i] = sm.id[e];
+        else if (in_lds)
+          s_key[i][t] = (uint32_t)jlo;
+        else
+          tkey[out0 + i] = jlo;
+        ++i;
       }
     }
   }
-  if (mode != 0 || !valid) return;
-  // rank the ray's pairs by (jlo, list position), 8 at a time, and move them
-  const int n = (int)(w - out0);
+  if (mode != 0) return;
+  // pass 2: rank of each pair by (jlo, list position), 8 pairs at a time
   for (int i0 = 0; i0 < n; i0 += 8) {
     int key[8], rank[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      key[q] = i0 + q < n ? tpj[out0 + i0 + q].x : INT_MAX;
+      key[q] = i0 + q < n ? (in_lds ? (int)(s_key[i0 + q][t] & 0xffffffu) : tkey[out0 + i0 + q]) : INT_MAX;
       rank[q] = 0;
     }
     for (int j = 0; j < n; ++j) {
-      const int kj = tpj[out0 + j].x;
+      const int kj = in_lds ? (int)(s_key[j][t] & 0xffffffu) : tkey[out0 + j];
 #pragma unroll
       for (int q = 0; q < 8; ++q) rank[q] += (kj < key[q] || (kj == key[q] && j < i0 + q)) ? 1 : 0;
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       if (i0 + q < n) {
-        const uint64_t src = out0 + i0 + q, dst = out0 + rank[q];
-        pa[dst] = tpa[src];
-        pb[dst] = tpb[src];
-        pj[dst] = tpj[src];
-        perm[src] = (uint32_t)dst;
+        if (in_lds)
+          s_key[i0 + q][t] = (uint32_t)key[q] | ((uint32_t)rank[q] << 24);
+        else
+          trank[out0 + i0 + q] = (uint32_t)rank[q];
+      }
+    }
+  }
+  // pass 3: every pair to its ranked slot, and the per-entry pair lists
+  i = 0;
+  for (uint64_t c0 = lb; c0 < le; c0 += kStage) {
+    const int nc = (int)min<uint64_t>(kStage, le - c0);
+    __syncthreads();
+    stage_chunk(sm, av, cam, c0, nc);
+    __syncthreads();
+    const int ic = i;
+    uint32_t word = 0;
+    for (int e = 0; e < nc; ++e) {
+      float a[3], b[3];
+      int jlo = 0, jhi = 0;
+      if (i < n && pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi)) {
+        const uint64_t dst = out0 + (in_lds ? (s_key[i][t] >> 24) : trank[out0 + i]);
+        pa[dst] = make_float4(a[0], a[1], a[2], __int_as_float(sm.id[e]));
+        pb[dst] = make_float4(b[0], b[1], b[2], __int_as_float((int)ray));
+        pj[dst] = make_int2(jlo, jhi);
+        ++i;
+        word |= 1u << (e & 31);
+      }
+      if ((e & 31) == 31 || e == nc - 1) {
+        s_bits[e >> 5][t] = word;
+        word = 0;
+      }
+    }
+    for (int e = 0; e < nc; ++e) {
+      const bool bit = (s_bits[e >> 5][t] >> (e & 31)) & 1u;
+      const unsigned long long m = __ballot(bit);
+      if (lane == 0) s_cnt[wave][e] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    int ii = ic;
+    for (int e = 0; e < nc; ++e) {
+      const bool bit = (s_bits[e >> 5][t] >> (e & 31)) & 1u;
+      const unsigned long long m = __ballot(bit);
+      if (bit) {
+        uint32_t base = 0;
+        for (int q = 0; q < wave; ++q) base += s_cnt[q][e];
+        const uint64_t pos = av.entry_off[c0 + e] + base + (uint32_t)__popcll(m & lt);
+        entry_pairs[pos] = (uint32_t)(out0 + (in_lds ? (s_key[ii][t] >> 24) : trank[out0 + ii]));
+        ++ii;
       }
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_remap_pairs(uint32_t *__restrict__ entry_pairs,
-                                                     const uint32_t *__restrict__ perm, uint64_t n) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) entry_pairs[i] = perm[entry_pairs[i]];
-}
-
-hipError_t launch_hit_emit(const AccelView &av, int mode, float4 *tpa, float4 *tpb, int2 *tpj, float4 *pa,
-                           float4 *pb, int2 *pj, uint32_t *perm, uint32_t *entry_pairs, int32_t *ids,
-                           uint64_t n_pairs, hipStream_t s) {
+hipError_t launch_hit_emit(const AccelView &av, int mode, int32_t *tkey, uint32_t *trank, float4 *pa, float4 *pb,
+                           int2 *pj, uint32_t *entry_pairs, int32_t *ids, hipStream_t s) {
   const int ntile = av.V * av.tiles_x * av.tiles_y;
   if (ntile == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hit_emit, dim3(ntile), dim3(kTileThreads), 0, s, av, mode, tpa, tpb, tpj, pa, pb, pj, perm,
+  hipLaunchKernelGGL(k_hit_emit, dim3(ntile), dim3(kTileThreads), 0, s, av, mode, tkey, trank, pa, pb, pj,
                      entry_pairs, ids);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || mode != 0 || n_pairs == 0) return e;
-  hipLaunchKernelGGL(k_remap_pairs, dim3(grid_for(n_pairs, 256)), dim3(256), 0, s, entry_pairs, perm, n_pairs);
   return hipGetLastError();
 }
 

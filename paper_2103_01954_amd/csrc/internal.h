@@ -26,22 +26,36 @@ struct DevCam {
 // Everything a kernel needs to address the per-frame structure.
 //
 // Culling lists: tile t (of V*T, view-major) owns tile_list[tile_off[t] ..
-// tile_off[t+1]), primitive ids in increasing order; entry_tile[g] is the tile
-// of list entry g.
+// tile_off[t+1]), primitive ids in increasing order.  Transposed: primitive k
+// owns the list entries prim_entries[prim_entry_off[k] .. prim_entry_off[k+1])
+// (ascending), grouped into backward work items item_off[k] .. item_off[k+1]
+// of at most kItemEntries entries each.
 // Pairs: ray r owns pairs [ray_off[r], ray_off[r+1]) sorted by (jlo, id);
 // pair i is (pa[i] = (a, primitive id), pb[i] = (b, ray index),
 // pj[i] = (jlo, jhi)): local ray y(t) = a + t b and its sample interval.
 // entry_pairs[entry_off[g] .. entry_off[g+1]) lists the pairs formed with
 // culling-list entry g (at most one per ray of the tile), in pixel order.
+// Per-ray constants of the backward: Tdot, the clamp weight ((1 - T_{S-1}) /
+// sigma_S for the sum rule, 1 - T* for the sequential combine) and the
+// clamping primitive of the sequential combine (-1: none).
+struct RayConst {
+  float tdot, w;
+  int32_t kstar, pad;
+};
+
 struct AccelView {
   int32_t V, W, H, N, M;
   int32_t tiles_x, tiles_y;
   float step, eps, t_near;
+  float fade_alpha, fade_beta; // opacity fade window (alpha == 0: none)
+  int32_t combine;             // 0: sum rule, 1: sequential in primitive-id order
   const DevCam *cams;          // [V]
   const float4 *xf;            // [N*3]: rows of A = diag(1/s) R^T, .w = t
   const uint64_t *tile_off;    // [V*T+1]
   const uint32_t *tile_list;   // [n_tile_pairs]
-  const uint32_t *entry_tile;  // [n_tile_pairs]
+  const uint64_t *prim_entry_off;  // [N+1]
+  const uint32_t *prim_entries;    // [n_tile_pairs]
+  const uint64_t *item_off;        // [N+1]
   const uint64_t *entry_off;   // [n_tile_pairs+1]
   const uint32_t *entry_pairs; // [n_pairs]
   const uint64_t *ray_off;     // [R+1]
@@ -57,6 +71,19 @@ struct AccelView {
   const uint64_t *tile_ray_off;  // [V*T+1] or nullptr
   const uint32_t *tile_rays;   // or nullptr
 };
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2):
+// workgroup b runs on XCD b % 8.  Launching kXcd * ceil(n / kXcd) workgroups and
+// mapping b -> (b % kXcd) * per + b / kXcd gives every XCD a contiguous band of
+// tiles, so neighbouring tiles (which share primitives) share an L2.  Returns
+// -1 for the padding workgroups.
+constexpr int kXcd = 8;
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int per = (n + kXcd - 1) / kXcd;
+  const int t = (b % kXcd) * per + b / kXcd;
+  return t < n ? t : -1;
+}
+__host__ __device__ __forceinline__ int xcd_grid(int n) { return kXcd * ((n + kXcd - 1) / kXcd); }
 
 // Ray of thread t of the workgroup of `tile`: its slot, view and pixel.
 // Returns false if the thread has no ray.
@@ -104,7 +131,15 @@ hipError_t launch_scan_u32_u64(const uint32_t *in, uint64_t *out, size_t n, void
 hipError_t launch_prep(const mvp_prims &p, const AccelView &av, float4 *xf, int4 *rect,
                        uint32_t *tile_cnt, hipStream_t s);
 hipError_t launch_tile_fill(const AccelView &av, const int4 *rect, uint32_t *cursor,
-                            uint32_t *tile_list, uint32_t *entry_tile, hipStream_t s);
+                            uint32_t *tile_list, hipStream_t s);
+// transpose the culling lists (count per primitive / fill), and count the
+// backward work items of every primitive
+hipError_t launch_prim_entry_count(const uint32_t *tile_list, uint64_t n, uint32_t *cnt, hipStream_t s);
+hipError_t launch_prim_entry_fill(const uint32_t *tile_list, uint64_t n, const uint64_t *off, uint32_t *cursor,
+                                  uint32_t *prim_entries, hipStream_t s);
+hipError_t launch_item_count(const uint64_t *prim_entry_off, int n_prim, int per_item, uint32_t *cnt,
+                             hipStream_t s);
+int backward_item_entries();
 // sort each segment [off[i], off[i+1]) of data (n_seg segments) ascending
 hipError_t launch_segment_sort(const uint64_t *off, uint32_t *data, int64_t n_seg, hipStream_t s);
 // ray subsets: count the sampled rays of every tile (flag: 1 = pixel id out of
@@ -115,17 +150,20 @@ hipError_t launch_ray_fill(const AccelView &av, uint32_t *cursor, uint32_t *tile
 // mode 1: every slab hit (debug), entry_cnt unused
 hipError_t launch_hit_count(const AccelView &av, int mode, uint32_t *ray_cnt, uint32_t *entry_cnt,
                             hipStream_t s);
-// mode 0 writes the pairs to tpa/tpb/tpj (temporary, culling-list order), then
-// to pa/pb/pj sorted by first sample; mode 1 writes only ids
-hipError_t launch_hit_emit(const AccelView &av, int mode, float4 *tpa, float4 *tpb, int2 *tpj, float4 *pa,
-                           float4 *pb, int2 *pj, uint32_t *perm, uint32_t *entry_pairs, int32_t *ids,
-                           uint64_t n_pairs, hipStream_t s);
+// mode 0 writes the pairs to pa/pb/pj, each ray's sorted by (first sample,
+// primitive id), and the per-entry pair lists; tkey/trank [n_pairs] are
+// scratch for rays with long lists.  Mode 1 writes only ids.
+hipError_t launch_hit_emit(const AccelView &av, int mode, int32_t *tkey, uint32_t *trank, float4 *pa, float4 *pb,
+                           int2 *pj, uint32_t *entry_pairs, int32_t *ids, hipStream_t s);
 
-hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, float *rgba, mvp_ray_aux *aux,
-                            unsigned long long *counters, hipStream_t s);
-// backward; rc is scratch of 2 floats per ray
-hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_entries,
-                            const mvp_ray_aux *aux, const float *grad_rgba, float2 *rc, float *g_pay,
-                            float *g_pos, float *g_rot, float *g_scale, hipStream_t s);
+// bg: optional background [rays,3] composited under the premultiplied colour
+hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, const float *bg, float *rgba,
+                            mvp_ray_aux *aux, unsigned long long *counters, hipStream_t s);
+// backward; rc is scratch of 2 floats per ray; bg/rgba/g_bg for a composited forward
+hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_items_max,
+                            const mvp_ray_aux *aux, const float *grad_rgba, const float *bg,
+                            const float *rgba, RayConst *rc, float *g_pay, float *g_pos, float *g_rot,
+                            float *g_scale, float *g_bg, hipStream_t s, hipEvent_t t0 = nullptr,
+                            hipEvent_t t1 = nullptr);   // optional events around the per-pair kernel
 
 }  // namespace mvp

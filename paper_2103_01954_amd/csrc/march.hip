@@ -7,7 +7,11 @@
 // (the global colour/opacity field), then accumulated with the clamp
 //   T + sigma_j dt <= 1 :  T += sigma_j dt,  I += C_j dt
 //   otherwise           :  I += C_j (1 - T) / sigma_j,  T = 1   (stop)
-// and the march stops once T > 1 - eps_early.
+// and the march stops once T > 1 - eps_early.  With the sequential combine
+// (combine == 1) a sample whose summed step saturates is instead taken one
+// primitive at a time in increasing id, each with its own clamp step: the
+// primitives before the clamping one k* add sigma_k c_k dt, k* adds
+// c_k* (1 - T) and the rest nothing; every other sample is the sum rule.
 //
 // Backward: the additive rule makes every sample's contribution independent
 // of the others except through the clamp, so the backward replays each
@@ -17,6 +21,9 @@
 //   dL/dsigma_kj = dt (Tdot + g . c_kj),   dL/dc_kj = dt sigma_kj g      (j < S)
 //   dL/dsigma_kS = (1 - T_{S-1}) (g . c_kS + Tdot) / sigma_S
 //   dL/dc_kS     = (1 - T_{S-1}) (sigma_kS / sigma_S) g
+// and for the sequential combine Tdot = -g . c_k*S, the primitives before k*
+// at S take the j < S formulas, dL/dc_k*S = (1 - T*) g with T* the opacity
+// just before k*, and dL/dsigma_k*S = 0.
 // The pairs are replayed one workgroup per (screen tile, primitive): channel
 // adjoints go to the 8 voxel corners with the trilinear weights, accumulated
 // in registers while consecutive samples stay in one cell and then in an LDS
@@ -64,6 +71,7 @@ __device__ __forceinline__ float4 lerp4(float4 a, float4 b, float f) {
 // the lower corner of the cell and the fractional offsets.
 struct Cell {
   int idx;      // (iz*M + iy)*M + ix of corner (0,0,0)
+  int i[3];     // ix, iy, iz of corner (0,0,0)
   float f[3];
 };
 
@@ -78,6 +86,7 @@ __device__ __forceinline__ Cell locate(const float4 &A, const float4 &B, float t
     int q = (int)floorf(u);
     q = min(max(q, 0), M - 2);
     i0[i] = q;
+    c.i[i] = q;
     c.f[i] = u - (float)q;
   }
   c.idx = (i0[2] * M + i0[1]) * M + i0[0];
@@ -165,6 +174,63 @@ __device__ __forceinline__ void load_corners(const void *pay, size_t b0, int M, 
 
 __device__ __forceinline__ int prim_of(const float4 &A) { return __float_as_int(A.w); }
 
+// Opacity fade window of Sec. 3.1.3 at the voxel centres of one axis,
+// w(i) = exp(-alpha |x_i|^beta), x_i = -1 + 2i/(M-1); W(ix,iy,iz) = w(ix) w(iy) w(iz).
+__device__ __forceinline__ void fill_fade(float *tab, int M, float alpha, float beta) {
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    const float x = -1.0f + 2.0f * (float)i / (float)(M - 1);
+    tab[i] = expf(-alpha * powf(fabsf(x), beta));
+  }
+}
+
+// Window of the 8 corners of a cell (corner q = dx + 2 dy + 4 dz).
+__device__ __forceinline__ void corner_fade(const float *tab, const Cell &c, float (&wq)[8]) {
+  const float wx[2] = {tab[c.i[0]], tab[c.i[0] + 1]};
+  const float wy[2] = {tab[c.i[1]], tab[c.i[1] + 1]};
+  const float wz[2] = {tab[c.i[2]], tab[c.i[2] + 1]};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) wq[q] = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
+}
+
+// RGBA of pair e at tau: trilinear payload of its primitive (opacity times the
+// fade window when FADE).
+template <bool BF16, bool FADE>
+__device__ __forceinline__ float4 sample_pair(const AccelView &av, const void *pay, const float *fade,
+                                              uint64_t e, float tau) {
+  const int M = av.M;
+  const float hM = 0.5f * (float)(M - 1);
+  const float4 A = av.pa[e];
+  const float4 B = av.pb[e];
+  const Cell c = locate(A, B, tau, M, hM);
+  float4 v[8];
+  load_corners<BF16>(pay, (size_t)prim_of(A) * M * M * M + c.idx, M, v);
+  if (FADE) {
+    float wq[8];
+    corner_fade(fade, c, wq);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q].w *= wq[q];
+  }
+  return trilerp(v, c);
+}
+
+// Among the pairs [e0, end) (sorted by first sample) that contain sample j,
+// the one with the smallest primitive id above `after`; end if none.
+__device__ __forceinline__ uint64_t next_by_id(const AccelView &av, uint64_t e0, uint64_t end, int j, int after) {
+  int best = INT_MAX;
+  uint64_t be = end;
+  for (uint64_t e = e0; e < end; ++e) {
+    const int2 r = av.pj[e];
+    if (r.x > j) break;
+    if (r.y < j) continue;
+    const int id = prim_of(av.pa[e]);
+    if (id > after && id < best) {
+      best = id;
+      be = e;
+    }
+  }
+  return be;
+}
+
 // Accumulated state of one ray.
 struct RayState {
   float T = 0.f, I0 = 0.f, I1 = 0.f, I2 = 0.f, t_prev = -1.0f;
@@ -194,6 +260,40 @@ __device__ __forceinline__ bool composite(RayState &st, int j, float sig, float 
   return true;
 }
 
+// Sequential combine at sample j, whose summed step saturates: the
+// primitives containing j in increasing id, each with its own clamp step.
+// Pairs containing j all lie in [e0, end).  Returns true to stop.
+template <bool BF16, bool FADE>
+__device__ bool seq_sample(const AccelView &av, const void *pay, const float *fade, uint64_t e0, uint64_t end,
+                           int j, RayState &st) {
+  const float dt = av.step;
+  const float tau = (float)j * dt;
+  const float T0 = st.T;
+  st.j_end = j;
+  int last = -1;
+  for (uint64_t e = next_by_id(av, e0, end, j, last); e < end; e = next_by_id(av, e0, end, j, last)) {
+    const float4 s = sample_pair<BF16, FADE>(av, pay, fade, e, tau);
+    const float Tn = st.T + s.w * dt;
+    if (Tn <= 1.0f) {
+      st.T = Tn;
+      st.I0 = fmaf(s.w * s.x, dt, st.I0);
+      st.I1 = fmaf(s.w * s.y, dt, st.I1);
+      st.I2 = fmaf(s.w * s.z, dt, st.I2);
+    } else {
+      const float u = 1.0f - st.T;
+      st.I0 = fmaf(s.x, u, st.I0);
+      st.I1 = fmaf(s.y, u, st.I1);
+      st.I2 = fmaf(s.z, u, st.I2);
+      st.t_prev = T0;
+      st.T = 1.0f;
+      return true;
+    }
+    last = prim_of(av.pa[e]);
+  }
+  // rounding kept every per-primitive step at or below 1: an ordinary sample
+  return st.T > 1.0f - av.eps;
+}
+
 // The samples J..J+kWin-1 of a ray are gathered pair by pair into per-sample
 // sums held in registers (a pair's 8 voxel corners stay in registers while
 // consecutive samples remain in one cell), then composited in sample order.
@@ -202,8 +302,9 @@ __device__ __forceinline__ bool composite(RayState &st, int j, float sig, float 
 // in primitive-id order.
 constexpr int kWin = 8;
 
-template <bool BF16>
-__device__ void march_ray(const AccelView &av, const void *pay, uint64_t beg, uint64_t end, RayState &st) {
+template <bool BF16, bool FADE>
+__device__ void march_ray(const AccelView &av, const void *pay, const float *fade, uint64_t beg, uint64_t end,
+                          RayState &st) {
   const float dt = av.step, lim = 1.0f - av.eps;
   const int M = av.M;
   const float hM = 0.5f * (float)(M - 1);
@@ -236,6 +337,12 @@ __device__ void march_ray(const AccelView &av, const void *pay, uint64_t beg, ui
           const Cell c = locate(A, B, tau, M, hM);
           if (c.idx != cur) {
             load_corners<BF16>(pay, kb + c.idx, M, v);
+            if (FADE) {
+              float wq[8];
+              corner_fade(fade, c, wq);
+#pragma unroll
+              for (int q = 0; q < 8; ++q) v[q].w *= wq[q];
+            }
             cur = c.idx;
           }
           const float4 s = trilerp(v, c);
@@ -253,7 +360,10 @@ __device__ void march_ray(const AccelView &av, const void *pay, uint64_t beg, ui
       if (!stop && cnt[w] > 0) {
         ++st.n_ray;
         st.n_prim += cnt[w];
-        stop = composite(st, J + w, as[w], ar[w], ag[w], ab[w], dt, lim);
+        if (av.combine && st.T + as[w] * dt > 1.0f)
+          stop = seq_sample<BF16, FADE>(av, pay, fade, e0, end, J + w, st);
+        else
+          stop = composite(st, J + w, as[w], ar[w], ag[w], ab[w], dt, lim);
       }
     }
     if (stop) break;
@@ -265,14 +375,18 @@ __device__ void march_ray(const AccelView &av, const void *pay, uint64_t beg, ui
   }
 }
 
-template <bool BF16>
+template <bool BF16, bool FADE>
 __global__ __launch_bounds__(kTileThreads) void k_march_fwd(AccelView av, const void *__restrict__ pay,
+                                                             const float *__restrict__ bg,
                                                              float4 *__restrict__ rgba,
                                                              mvp_ray_aux *__restrict__ aux,
                                                              unsigned long long *__restrict__ counters) {
   __shared__ int s_list[kTileThreads];
   __shared__ int s_wave[kTileThreads / kWave];
-  const int tile = blockIdx.x;
+  extern __shared__ float s_fade[];   // [M] when FADE
+  const int tile = xcd_tile(blockIdx.x, av.V * av.tiles_x * av.tiles_y);
+  if (tile < 0) return;
+  if (FADE) fill_fade(s_fade, av.M, av.fade_alpha, av.fade_beta);   // visible after compact_tile's barrier
   int total;
   {
     size_t ray;
@@ -282,7 +396,9 @@ __global__ __launch_bounds__(kTileThreads) void k_march_fwd(AccelView av, const 
     if (valid) {
       act = av.ray_off[ray + 1] > av.ray_off[ray];
       if (!act) {
-        rgba[ray] = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (bg) o = make_float4(bg[3 * ray], bg[3 * ray + 1], bg[3 * ray + 2], 0.f);
+        rgba[ray] = o;
         if (aux) aux[ray] = mvp_ray_aux{-1, -1.0f};
       }
     }
@@ -293,7 +409,13 @@ __global__ __launch_bounds__(kTileThreads) void k_march_fwd(AccelView av, const 
     size_t ray;
     int v, px, py;
     tile_ray(av, tile, s_list[threadIdx.x], &ray, &v, &px, &py);
-    march_ray<BF16>(av, pay, av.ray_off[ray], av.ray_off[ray + 1], st);
+    march_ray<BF16, FADE>(av, pay, s_fade, av.ray_off[ray], av.ray_off[ray + 1], st);
+    if (bg) {   // composite over the background: I + (1 - A) B
+      const float u = 1.0f - st.T;
+      st.I0 = fmaf(u, bg[3 * ray], st.I0);
+      st.I1 = fmaf(u, bg[3 * ray + 1], st.I1);
+      st.I2 = fmaf(u, bg[3 * ray + 2], st.I2);
+    }
     rgba[ray] = make_float4(st.I0, st.I1, st.I2, st.T);
     if (aux) aux[ray] = mvp_ray_aux{st.j_end, st.t_prev};
   }
@@ -307,16 +429,21 @@ __global__ __launch_bounds__(kTileThreads) void k_march_fwd(AccelView av, const 
   }
 }
 
-hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, float *rgba, mvp_ray_aux *aux,
-                            unsigned long long *counters, hipStream_t s) {
+hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, const float *bg, float *rgba,
+                            mvp_ray_aux *aux, unsigned long long *counters, hipStream_t s) {
   const int ntile = av.V * av.tiles_x * av.tiles_y;
   if (ntile == 0) return hipSuccess;
-  if (p.payload_dtype == MVP_BF16)
-    hipLaunchKernelGGL(k_march_fwd<true>, dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
-                       (float4 *)rgba, aux, counters);
-  else
-    hipLaunchKernelGGL(k_march_fwd<false>, dim3(ntile), dim3(kTileThreads), 0, s, av, p.payload,
-                       (float4 *)rgba, aux, counters);
+  const bool fade = av.fade_alpha > 0.f;
+  const size_t shm = fade ? (size_t)av.M * sizeof(float) : 0;
+#define MVP_FWD(B, F)                                                                                  \
+  hipLaunchKernelGGL((k_march_fwd<B, F>), dim3(xcd_grid(ntile)), dim3(kTileThreads), shm, s, av, p.payload, bg, \
+                     (float4 *)rgba, aux, counters)
+  if (p.payload_dtype == MVP_BF16) {
+    if (fade) MVP_FWD(true, true); else MVP_FWD(true, false);
+  } else {
+    if (fade) MVP_FWD(false, true); else MVP_FWD(false, false);
+  }
+#undef MVP_FWD
   return hipGetLastError();
 }
 
@@ -324,44 +451,77 @@ hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, float *rgba
 // backward
 // ---------------------------------------------------------------------------
 
-// Per-ray constants of the adjoint: (Tdot, (1 - T_{S-1}) / sigma_S).  Tdot is
-// dL/dA for an unclamped ray and -g . C_S/sigma_S for a ray clamped at its
-// last sample S (recomputed here from the pairs open at S).
-template <bool BF16>
+// Per-ray constants of the adjoint.  Tdot is dL/dA for an unclamped ray and
+// -g . C_S/sigma_S for a ray clamped at its last sample S, with the weight
+// (1 - T_{S-1}) / sigma_S (recomputed here from the pairs open at S).  For
+// the sequential combine the clamping primitive k* is found again by
+// replaying the per-primitive steps of S from T_{S-1} with the forward's
+// arithmetic; then Tdot = -g . c_k*, the weight is 1 - T* and kstar = k*.
+// With a background B the output colour is I + (1 - A) B: the upstream of A
+// becomes dL/dA - g . B, and dL/dB = (1 - A) g is accumulated here.
+template <bool BF16, bool FADE>
 __global__ __launch_bounds__(256) void k_bwd_rays(AccelView av, const void *__restrict__ pay,
                                                   const mvp_ray_aux *__restrict__ aux,
                                                   const float4 *__restrict__ grad_rgba,
-                                                  float2 *__restrict__ rc, size_t R) {
+                                                  const float *__restrict__ bg, const float4 *__restrict__ rgba,
+                                                  RayConst *__restrict__ rc, float *__restrict__ g_bg, size_t R) {
+  extern __shared__ float s_fade[];
+  if (FADE) {
+    fill_fade(s_fade, av.M, av.fade_alpha, av.fade_beta);
+    __syncthreads();
+  }
   const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
   const mvp_ray_aux ax = aux[r];
   const float4 g = grad_rgba[r];
   float tdot = g.w, wsig = 0.f;
-  if (ax.j_end >= 0 && ax.t_prev >= 0.f) {
-    const int M = av.M;
-    const float hM = 0.5f * (float)(M - 1);
-    const size_t M3 = (size_t)M * M * M;
-    const float tau = (float)ax.j_end * av.step;
-    float sig = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-    for (uint64_t e = av.ray_off[r]; e < av.ray_off[r + 1]; ++e) {
-      const int2 jr = av.pj[e];
-      if (jr.x > ax.j_end) break;          // sorted by first sample
-      if (jr.y < ax.j_end) continue;
-      const float4 A = av.pa[e];
-      const float4 B = av.pb[e];
-      const Cell c = locate(A, B, tau, M, hM);
-      float4 v[8];
-      load_corners<BF16>(pay, (size_t)prim_of(A) * M3 + c.idx, M, v);
-      const float4 s = trilerp(v, c);
-      sig += s.w;
-      c0 = fmaf(s.w, s.x, c0);
-      c1 = fmaf(s.w, s.y, c1);
-      c2 = fmaf(s.w, s.z, c2);
+  if (bg) {
+    const float b0 = bg[3 * r], b1 = bg[3 * r + 1], b2 = bg[3 * r + 2];
+    tdot -= g.x * b0 + g.y * b1 + g.z * b2;
+    if (g_bg) {
+      const float u = 1.0f - rgba[r].w;
+      g_bg[3 * r] += u * g.x;
+      g_bg[3 * r + 1] += u * g.y;
+      g_bg[3 * r + 2] += u * g.z;
     }
-    tdot = -(g.x * (c0 / sig) + g.y * (c1 / sig) + g.z * (c2 / sig));
-    wsig = (1.0f - ax.t_prev) / sig;
   }
-  rc[r] = make_float2(tdot, wsig);
+  int kstar = -1;
+  if (ax.j_end >= 0 && ax.t_prev >= 0.f) {
+    const float tau = (float)ax.j_end * av.step;
+    const uint64_t b = av.ray_off[r], end = av.ray_off[r + 1];
+    if (av.combine) {
+      float T = ax.t_prev;
+      int last = -1;
+      for (uint64_t e = next_by_id(av, b, end, ax.j_end, last); e < end;
+           e = next_by_id(av, b, end, ax.j_end, last)) {
+        const float4 s = sample_pair<BF16, FADE>(av, pay, s_fade, e, tau);
+        const float Tn = T + s.w * av.step;
+        last = prim_of(av.pa[e]);
+        if (Tn > 1.0f) {
+          kstar = last;
+          tdot = -(g.x * s.x + g.y * s.y + g.z * s.z);
+          wsig = 1.0f - T;
+          break;
+        }
+        T = Tn;
+      }
+    } else {
+      float sig = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+      for (uint64_t e = b; e < end; ++e) {
+        const int2 jr = av.pj[e];
+        if (jr.x > ax.j_end) break;          // sorted by first sample
+        if (jr.y < ax.j_end) continue;
+        const float4 s = sample_pair<BF16, FADE>(av, pay, s_fade, e, tau);
+        sig += s.w;
+        c0 = fmaf(s.w, s.x, c0);
+        c1 = fmaf(s.w, s.y, c1);
+        c2 = fmaf(s.w, s.z, c2);
+      }
+      tdot = -(g.x * (c0 / sig) + g.y * (c1 / sig) + g.z * (c2 / sig));
+      wsig = (1.0f - ax.t_prev) / sig;
+    }
+  }
+  rc[r] = RayConst{tdot, wsig, kstar, 0};
 }
 
 struct BwdOut {
@@ -370,8 +530,11 @@ struct BwdOut {
 
 // Add the 32 register-accumulated corner gradients of one cell: into the LDS
 // copy of the primitive's gradient (LDS_ACC) or straight into device memory.
-template <bool LDS_ACC>
-__device__ __forceinline__ void flush_cell(float *dst, size_t cell, int M, const float (&acc)[8][4]) {
+// With the fade window the opacity gradient of a stored voxel is the window
+// times the gradient of its windowed value.
+template <bool LDS_ACC, bool FADE>
+__device__ __forceinline__ void flush_cell(float *dst, size_t cell, int M, const float (&acc)[8][4],
+                                           const float (&wq)[8]) {
   const size_t MM = (size_t)M * M;
   const size_t off[8] = {0, 1, (size_t)M, (size_t)M + 1, MM, MM + 1, MM + M, MM + M + 1};
 #pragma unroll
@@ -379,164 +542,231 @@ __device__ __forceinline__ void flush_cell(float *dst, size_t cell, int M, const
     float *p = dst + (cell + off[q]) * 4;
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) {
+      const float x = (FADE && ch == 3) ? acc[q][ch] * wq[q] : acc[q][ch];
       if (LDS_ACC)
-        atomicAdd(p + ch, acc[q][ch]);
+        atomicAdd(p + ch, x);
       else
-        unsafeAtomicAdd(p + ch, acc[q][ch]);
+        unsafeAtomicAdd(p + ch, x);
     }
   }
 }
 
-// Backward, one workgroup per culling-list entry (tile, primitive k): the
-// tile's rays that form a pair with k replay their samples inside k.  The
-// payload gradient of k is accumulated in LDS (LDS_ACC) and added to device
-// memory once per workgroup; the pose gradient is reduced over the workgroup
-// and added with 15 atomics.
-template <bool BF16, bool LDS_ACC>
-__global__ __launch_bounds__(kTileThreads) void k_bwd_entries(AccelView av, const float *__restrict__ rot,
-                                                               const float *__restrict__ scale,
-                                                               const void *__restrict__ pay,
-                                                               const mvp_ray_aux *__restrict__ aux,
-                                                               const float4 *__restrict__ grad_rgba,
-                                                               const float2 *__restrict__ rc,
-                                                               int64_t n_entries, BwdOut out) {
-  extern __shared__ float s_grad[];
-  __shared__ float s_pose[kTileThreads / kWave][16];
+// Replay one (ray, primitive k) pair backward: channel adjoints to the 8
+// voxel corners (registers while the samples stay in one cell, then gdst:
+// the LDS copy of k's gradient or device memory) and the pose chain of the
+// pair added to P (dL/dt 3, dL/dR 9 row-major, dL/ds 3).
+template <bool BF16, bool LDS_ACC, bool FADE>
+__device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__restrict__ rot,
+                                         const float *__restrict__ scale, const void *__restrict__ pay,
+                                         const mvp_ray_aux *__restrict__ aux, const float4 *__restrict__ grad_rgba,
+                                         const RayConst *__restrict__ rc, uint32_t e, int k, float *gdst,
+                                         const float *s_fade, bool pose, float (&P)[15]) {
   const int M = av.M;
   const float hM = 0.5f * (float)(M - 1);
   const size_t M3 = (size_t)M * M * M;
-  const size_t MM = (size_t)M * M;
-  const int nacc = (int)(M3 * 4);
   const float dt = av.step;
+  const float4 A = av.pa[e];
+  const float4 B = av.pb[e];
+  const int2 jr = av.pj[e];
+  const int ray = __float_as_int(B.w);
+  const mvp_ray_aux ax = aux[ray];
+  const float4 g = grad_rgba[ray];
+  const RayConst rcv = rc[ray];
+  const float tdot = rcv.tdot, wsig = rcv.w;
+  // sum rule: sample S uses the clamp formulas; sequential: only k* does
+  // (primitives before it are ordinary steps, those after it add nothing)
+  const bool clamped = ax.t_prev >= 0.f && (!av.combine || rcv.kstar >= 0);
+  const bool seq = av.combine != 0;
+  const int jh = min(jr.y, ax.j_end);
+  const size_t kb = (size_t)k * M3;
+  float G0 = 0.f, G1 = 0.f, G2 = 0.f, H0 = 0.f, H1 = 0.f, H2 = 0.f;
+  int cur = -1;
+  float4 cv[8];
+  float acc[8][4];
+  float wq[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) wq[q] = 1.0f;
+  for (int j = jr.x; j <= jh; ++j) {
+    const float tau = (float)j * dt;
+    const Cell c = locate(A, B, tau, M, hM);
+    if (c.idx != cur) {
+      if (cur >= 0 && gdst) flush_cell<LDS_ACC, FADE>(gdst, cur, M, acc, wq);
+      load_corners<BF16>(pay, kb + c.idx, M, cv);
+      if (FADE) {
+        corner_fade(s_fade, c, wq);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cv[q].w *= wq[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
+      cur = c.idx;
+    }
+    const float fx = c.f[0], fy = c.f[1], fz = c.f[2];
+    const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
+    float w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) w[q] = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
+    float r = 0.f, gg = 0.f, b = 0.f, sg = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      r = fmaf(w[q], cv[q].x, r);
+      gg = fmaf(w[q], cv[q].y, gg);
+      b = fmaf(w[q], cv[q].z, b);
+      sg = fmaf(w[q], cv[q].w, sg);
+    }
+    const float gc = g.x * r + g.y * gg + g.z * b;
+    float a3, ws;   // dL/dsigma and the factor of g in dL/d(rgb) for this prim-sample
+    if (clamped && j == ax.j_end && (!seq || k >= rcv.kstar)) {
+      a3 = seq ? 0.f : wsig * (gc + tdot);
+      ws = seq ? (k == rcv.kstar ? wsig : 0.f) : wsig * sg;
+    } else {
+      a3 = dt * (tdot + gc);
+      ws = dt * sg;
+    }
+    const float a0 = ws * g.x, a1 = ws * g.y, a2 = ws * g.z;
+    float sc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      acc[q][0] = fmaf(w[q], a0, acc[q][0]);
+      acc[q][1] = fmaf(w[q], a1, acc[q][1]);
+      acc[q][2] = fmaf(w[q], a2, acc[q][2]);
+      acc[q][3] = fmaf(w[q], a3, acc[q][3]);
+      sc[q] = a0 * cv[q].x + a1 * cv[q].y + a2 * cv[q].z + a3 * cv[q].w;
+    }
+    // gradient of the trilinear interpolant of sc with respect to y
+    const float gx = hM * (wy[0] * wz[0] * (sc[1] - sc[0]) + wy[1] * wz[0] * (sc[3] - sc[2]) +
+                           wy[0] * wz[1] * (sc[5] - sc[4]) + wy[1] * wz[1] * (sc[7] - sc[6]));
+    const float gyv = hM * (wx[0] * wz[0] * (sc[2] - sc[0]) + wx[1] * wz[0] * (sc[3] - sc[1]) +
+                            wx[0] * wz[1] * (sc[6] - sc[4]) + wx[1] * wz[1] * (sc[7] - sc[5]));
+    const float gz = hM * (wx[0] * wy[0] * (sc[4] - sc[0]) + wx[1] * wy[0] * (sc[5] - sc[1]) +
+                           wx[0] * wy[1] * (sc[6] - sc[2]) + wx[1] * wy[1] * (sc[7] - sc[3]));
+    G0 += gx;
+    G1 += gyv;
+    G2 += gz;
+    H0 = fmaf(tau, gx, H0);
+    H1 = fmaf(tau, gyv, H1);
+    H2 = fmaf(tau, gz, H2);
+  }
+  if (cur >= 0 && gdst) flush_cell<LDS_ACC, FADE>(gdst, cur, M, acc, wq);
+  if (!pose) return;
+  // y = A (o + tau d - t), A = diag(1/s) R^T; d is the unit pixel ray
+  int rv, px, py;
+  slot_pixel(av, (size_t)ray, &rv, &px, &py);
+  const DevCam &cam = av.cams[rv];
+  const float u = (float)px + 0.5f, wv = (float)py + 0.5f;
+  float d[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) d[i] = cam.P[3 * i] * u + cam.P[3 * i + 1] * wv + cam.P[3 * i + 2];
+  const float inv = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) d[i] *= inv;
+  const float G[3] = {G0, G1, G2}, H[3] = {H0, H1, H2};
+  float Am[9], t[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float4 row = av.xf[3 * (size_t)k + i];
+    Am[3 * i] = row.x; Am[3 * i + 1] = row.y; Am[3 * i + 2] = row.z; t[i] = row.w;
+  }
+  const float p[3] = {cam.o[0] - t[0], cam.o[1] - t[1], cam.o[2] - t[2]};
+  float Rm[9], sk[3];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Rm[i] = rot[9 * (size_t)k + i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) sk[i] = scale[3 * (size_t)k + i];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) P[m] -= Am[m] * G[0] + Am[3 + m] * G[1] + Am[6 + m] * G[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    float rp = 0.f;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const float Pm = fmaf(p[m], G[i], d[m] * H[i]);
+      P[3 + 3 * m + i] += Pm / sk[i];
+      rp = fmaf(Rm[3 * m + i], Pm, rp);
+    }
+    P[12 + i] -= rp / (sk[i] * sk[i]);
+  }
+}
+
+// Culling-list entries per backward work item.
+constexpr int kItemEntries = 64;
+
+// Backward, one workgroup per work item: up to kItemEntries culling-list
+// entries (tile, primitive k) of one primitive.  The pairs of those entries
+// (at most one per ray of each tile) are spread over the workgroup's threads;
+// the payload gradient of k is accumulated in LDS (LDS_ACC) and added to
+// device memory once per item, the pose gradient is reduced over the
+// workgroup and added with 15 atomics.
+template <bool BF16, bool LDS_ACC, bool FADE>
+__global__ __launch_bounds__(kTileThreads) void k_bwd_items(AccelView av, const float *__restrict__ rot,
+                                                             const float *__restrict__ scale,
+                                                             const void *__restrict__ pay,
+                                                             const mvp_ray_aux *__restrict__ aux,
+                                                             const float4 *__restrict__ grad_rgba,
+                                                             const RayConst *__restrict__ rc, BwdOut out) {
+  extern __shared__ float s_dyn[];      // [M^3*4] gradient (LDS_ACC), then [M] fade window (FADE)
+  __shared__ float s_pose[kTileThreads / kWave][16];
+  __shared__ uint64_t s_start[kItemEntries];
+  __shared__ uint32_t s_pre[kItemEntries + 1];
+  __shared__ int s_prim;
+  const int M = av.M;
+  const size_t M3 = (size_t)M * M * M;
+  const int nacc = (int)(M3 * 4);
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const bool pose = out.pos || out.rot || out.scale;
-
-  for (int64_t gi = blockIdx.x; gi < n_entries; gi += gridDim.x) {
-    const uint64_t e0 = av.entry_off[gi], e1 = av.entry_off[gi + 1];
-    if (e1 == e0) continue;                              // uniform over the workgroup
-    const int k = (int)av.tile_list[gi];
-    if (LDS_ACC && out.pay) {
-      for (int i = threadIdx.x; i < nacc; i += kTileThreads) s_grad[i] = 0.f;
-      __syncthreads();
+  float *s_grad = s_dyn;
+  float *s_fade = s_dyn + ((LDS_ACC && out.pay) ? nacc : 0);
+  if (FADE) {
+    fill_fade(s_fade, M, av.fade_alpha, av.fade_beta);
+    __syncthreads();
+  }
+  const uint64_t n_items = av.item_off[av.N];
+  for (uint64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    if (threadIdx.x == 0) {   // primitive of the item: last p with item_off[p] <= it
+      int lo = 0, hi = av.N - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (av.item_off[mid] <= it) lo = mid; else hi = mid - 1;
+      }
+      s_prim = lo;
     }
+    __syncthreads();
+    const int k = s_prim;
+    const uint64_t chunk = it - av.item_off[k];
+    const uint64_t eb = av.prim_entry_off[k] + chunk * kItemEntries;
+    const int nent = (int)min<uint64_t>(kItemEntries, av.prim_entry_off[k + 1] - eb);
+    if (wave == 0) {          // the entries' pair ranges and their prefix sums
+      uint32_t cnt = 0;
+      if (lane < nent) {
+        const uint32_t g = av.prim_entries[eb + lane];
+        s_start[lane] = av.entry_off[g];
+        cnt = (uint32_t)(av.entry_off[g + 1] - av.entry_off[g]);
+      }
+      uint32_t incl = cnt;
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
+      }
+      if (lane == 0) s_pre[0] = 0;
+      if (lane < kItemEntries) s_pre[lane + 1] = incl;
+    }
+    if (LDS_ACC && out.pay)
+      for (int i = threadIdx.x; i < nacc; i += kTileThreads) s_grad[i] = 0.f;
+    __syncthreads();
+    const uint32_t total = s_pre[nent];
+    float *gdst = out.pay ? (LDS_ACC ? s_grad : out.pay + (size_t)k * M3 * 4) : nullptr;
     float P[15];
 #pragma unroll
     for (int i = 0; i < 15; ++i) P[i] = 0.f;
-    if (threadIdx.x < e1 - e0) {
-      const uint32_t e = av.entry_pairs[e0 + threadIdx.x];
-      const float4 A = av.pa[e];
-      const float4 B = av.pb[e];
-      const int2 jr = av.pj[e];
-      const int ray = __float_as_int(B.w);
-      const mvp_ray_aux ax = aux[ray];
-      const float4 g = grad_rgba[ray];
-      const float2 c2 = rc[ray];
-      const float tdot = c2.x, wsig = c2.y;
-      const bool clamped = ax.t_prev >= 0.f;
-      const int jh = min(jr.y, ax.j_end);
-      const size_t kb = (size_t)k * M3;
-      float *gdst = out.pay ? (LDS_ACC ? s_grad : out.pay + kb * 4) : nullptr;
-      float G0 = 0.f, G1 = 0.f, G2 = 0.f, H0 = 0.f, H1 = 0.f, H2 = 0.f;
-      int cur = -1;
-      float4 cv[8];
-      float acc[8][4];
-      for (int j = jr.x; j <= jh; ++j) {
-        const float tau = (float)j * dt;
-        const Cell c = locate(A, B, tau, M, hM);
-        if (c.idx != cur) {
-          if (cur >= 0 && gdst) flush_cell<LDS_ACC>(gdst, cur, M, acc);
-          load_corners<BF16>(pay, kb + c.idx, M, cv);
-#pragma unroll
-          for (int q = 0; q < 8; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
-          cur = c.idx;
-        }
-        const float fx = c.f[0], fy = c.f[1], fz = c.f[2];
-        const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
-        float w[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) w[q] = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
-        float r = 0.f, gg = 0.f, b = 0.f, s = 0.f;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          r = fmaf(w[q], cv[q].x, r);
-          gg = fmaf(w[q], cv[q].y, gg);
-          b = fmaf(w[q], cv[q].z, b);
-          s = fmaf(w[q], cv[q].w, s);
-        }
-        const float gc = g.x * r + g.y * gg + g.z * b;
-        float a3, ws;   // dL/dsigma and the factor of g in dL/d(rgb) for this prim-sample
-        if (clamped && j == ax.j_end) {
-          a3 = wsig * (gc + tdot);
-          ws = wsig * s;
-        } else {
-          a3 = dt * (tdot + gc);
-          ws = dt * s;
-        }
-        const float a0 = ws * g.x, a1 = ws * g.y, a2 = ws * g.z;
-        float sc[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          acc[q][0] = fmaf(w[q], a0, acc[q][0]);
-          acc[q][1] = fmaf(w[q], a1, acc[q][1]);
-          acc[q][2] = fmaf(w[q], a2, acc[q][2]);
-          acc[q][3] = fmaf(w[q], a3, acc[q][3]);
-          sc[q] = a0 * cv[q].x + a1 * cv[q].y + a2 * cv[q].z + a3 * cv[q].w;
-        }
-        // gradient of the trilinear interpolant of sc with respect to y
-        const float gx = hM * (wy[0] * wz[0] * (sc[1] - sc[0]) + wy[1] * wz[0] * (sc[3] - sc[2]) +
-                               wy[0] * wz[1] * (sc[5] - sc[4]) + wy[1] * wz[1] * (sc[7] - sc[6]));
-        const float gyv = hM * (wx[0] * wz[0] * (sc[2] - sc[0]) + wx[1] * wz[0] * (sc[3] - sc[1]) +
-                                wx[0] * wz[1] * (sc[6] - sc[4]) + wx[1] * wz[1] * (sc[7] - sc[5]));
-        const float gz = hM * (wx[0] * wy[0] * (sc[4] - sc[0]) + wx[1] * wy[0] * (sc[5] - sc[1]) +
-                               wx[0] * wy[1] * (sc[6] - sc[2]) + wx[1] * wy[1] * (sc[7] - sc[3]));
-        G0 += gx;
-        G1 += gyv;
-        G2 += gz;
-        H0 = fmaf(tau, gx, H0);
-        H1 = fmaf(tau, gyv, H1);
-        H2 = fmaf(tau, gz, H2);
+    for (uint32_t i = threadIdx.x; i < total; i += kTileThreads) {
+      int lo = 0, hi = nent - 1;   // entry of flattened pair i: last q with s_pre[q] <= i
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= i) lo = mid; else hi = mid - 1;
       }
-      if (cur >= 0 && gdst) flush_cell<LDS_ACC>(gdst, cur, M, acc);
-
-      if (pose) {
-        // y = A (o + tau d - t), A = diag(1/s) R^T; d is the unit pixel ray
-        int rv, px, py;
-        slot_pixel(av, (size_t)ray, &rv, &px, &py);
-        const DevCam &cam = av.cams[rv];
-        const float u = (float)px + 0.5f, wv = (float)py + 0.5f;
-        float d[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) d[i] = cam.P[3 * i] * u + cam.P[3 * i + 1] * wv + cam.P[3 * i + 2];
-        const float inv = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) d[i] *= inv;
-        const float G[3] = {G0, G1, G2}, H[3] = {H0, H1, H2};
-        float Am[9], t[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const float4 row = av.xf[3 * (size_t)k + i];
-          Am[3 * i] = row.x; Am[3 * i + 1] = row.y; Am[3 * i + 2] = row.z; t[i] = row.w;
-        }
-        const float p[3] = {cam.o[0] - t[0], cam.o[1] - t[1], cam.o[2] - t[2]};
-        float Rm[9], sk[3];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) Rm[i] = rot[9 * (size_t)k + i];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) sk[i] = scale[3 * (size_t)k + i];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) P[m] = -(Am[m] * G[0] + Am[3 + m] * G[1] + Am[6 + m] * G[2]);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          float rp = 0.f;
-#pragma unroll
-          for (int m = 0; m < 3; ++m) {
-            const float Pm = fmaf(p[m], G[i], d[m] * H[i]);
-            P[3 + 3 * m + i] = Pm / sk[i];
-            rp = fmaf(Rm[3 * m + i], Pm, rp);
-          }
-          P[12 + i] = -rp / (sk[i] * sk[i]);
-        }
-      }
+      const uint32_t e = av.entry_pairs[s_start[lo] + (i - s_pre[lo])];
+      bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, e, k, gdst, s_fade, pose, P);
     }
     if (pose) {
 #pragma unroll
@@ -548,7 +778,7 @@ __global__ __launch_bounds__(kTileThreads) void k_bwd_entries(AccelView av, cons
       }
     }
     __syncthreads();
-    if (pose && threadIdx.x < 15) {
+    if (pose && threadIdx.x < 15 && total > 0) {
       float x = 0.f;
 #pragma unroll
       for (int w = 0; w < kTileThreads / kWave; ++w) x += s_pose[w][threadIdx.x];
@@ -561,58 +791,73 @@ __global__ __launch_bounds__(kTileThreads) void k_bwd_entries(AccelView av, cons
         if (out.scale) unsafeAtomicAdd(out.scale + 3 * (size_t)k + (i - 12), x);
       }
     }
-    if (LDS_ACC && out.pay) {
+    if (LDS_ACC && out.pay && total > 0) {
       float *dst = out.pay + M3 * 4 * (size_t)k;
       for (int i = threadIdx.x; i < nacc; i += kTileThreads) {
         const float x = s_grad[i];
         if (x != 0.f) unsafeAtomicAdd(dst + i, x);
       }
     }
-    __syncthreads();   // LDS is reused by the next entry
+    __syncthreads();   // LDS is reused by the next item
   }
-  (void)MM;
 }
 
 // Largest per-primitive gradient (M^3 x 4 floats) accumulated in LDS.
 constexpr size_t kLdsGradBytes = 64 * 1024;
 
-hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_entries,
-                            const mvp_ray_aux *aux, const float *grad_rgba, float2 *rc, float *g_pay,
-                            float *g_pos, float *g_rot, float *g_scale, hipStream_t s) {
+hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_items_max,
+                            const mvp_ray_aux *aux, const float *grad_rgba, const float *bg,
+                            const float *rgba, RayConst *rc, float *g_pay, float *g_pos, float *g_rot,
+                            float *g_scale, float *g_bg, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   const size_t R = (size_t)av.n_slots;
-  if (R == 0 || p.n_prim == 0 || n_entries == 0) return hipSuccess;
+  if (R == 0) return hipSuccess;
   const bool bf16 = p.payload_dtype == MVP_BF16;
+  const bool fade = av.fade_alpha > 0.f;
+  const size_t fade_shm = fade ? (size_t)p.M * sizeof(float) : 0;
   const unsigned rb = (unsigned)((R + 255) / 256);
-  if (bf16)
-    hipLaunchKernelGGL(k_bwd_rays<true>, dim3(rb), dim3(256), 0, s, av, p.payload, aux, (const float4 *)grad_rgba, rc, R);
-  else
-    hipLaunchKernelGGL(k_bwd_rays<false>, dim3(rb), dim3(256), 0, s, av, p.payload, aux, (const float4 *)grad_rgba, rc, R);
+#define MVP_RAYS(B, F)                                                                                        \
+  hipLaunchKernelGGL((k_bwd_rays<B, F>), dim3(rb), dim3(256), fade_shm, s, av, p.payload, aux,               \
+                     (const float4 *)grad_rgba, bg, (const float4 *)rgba, rc, g_bg, R)
+  if (bf16) {
+    if (fade) MVP_RAYS(true, true); else MVP_RAYS(true, false);
+  } else {
+    if (fade) MVP_RAYS(false, true); else MVP_RAYS(false, false);
+  }
+#undef MVP_RAYS
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || p.n_prim == 0 || n_items_max == 0) return e;
   const size_t M3 = (size_t)p.M * p.M * p.M;
   const size_t lds = M3 * 16;
   bool in_lds = lds <= kLdsGradBytes;
   if (in_lds && g_pay) {
     // allow more than the default dynamic LDS per workgroup (gfx950 has 160 KB)
-    const void *fn = bf16 ? (const void *)k_bwd_entries<true, true> : (const void *)k_bwd_entries<false, true>;
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsGradBytes) != hipSuccess) {
+    const void *fn = bf16 ? (fade ? (const void *)k_bwd_items<true, true, true> : (const void *)k_bwd_items<true, true, false>)
+                          : (fade ? (const void *)k_bwd_items<false, true, true> : (const void *)k_bwd_items<false, true, false>);
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsGradBytes + 4096)) != hipSuccess) {
       (void)hipGetLastError();
-      in_lds = lds <= 48 * 1024;
+      in_lds = lds + fade_shm <= 48 * 1024;
     }
   }
-  const unsigned grid = (unsigned)std::min<int64_t>(n_entries, 1 << 20);
+  const unsigned grid = (unsigned)std::min<int64_t>(n_items_max, 1 << 20);
   BwdOut out{g_pay, g_pos, g_rot, g_scale};
-  const size_t shm = in_lds && g_pay ? lds : 0;
-#define MVP_BWD(B, L)                                                                                   \
-  hipLaunchKernelGGL((k_bwd_entries<B, L>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale, \
-                     p.payload, aux, (const float4 *)grad_rgba, (const float2 *)rc, n_entries, out)
+  const size_t shm = (in_lds && g_pay ? lds : 0) + fade_shm;
+  if (t0) (void)hipEventRecord(t0, s);
+#define MVP_BWD(B, L, F)                                                                                  \
+  hipLaunchKernelGGL((k_bwd_items<B, L, F>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale,   \
+                     p.payload, aux, (const float4 *)grad_rgba, rc, out)
   if (bf16) {
-    if (in_lds) MVP_BWD(true, true); else MVP_BWD(true, false);
+    if (in_lds) { if (fade) MVP_BWD(true, true, true); else MVP_BWD(true, true, false); }
+    else { if (fade) MVP_BWD(true, false, true); else MVP_BWD(true, false, false); }
   } else {
-    if (in_lds) MVP_BWD(false, true); else MVP_BWD(false, false);
+    if (in_lds) { if (fade) MVP_BWD(false, true, true); else MVP_BWD(false, true, false); }
+    else { if (fade) MVP_BWD(false, false, true); else MVP_BWD(false, false, false); }
   }
 #undef MVP_BWD
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (t1) (void)hipEventRecord(t1, s);
+  return e;
 }
+
+int backward_item_entries() { return kItemEntries; }
 
 }  // namespace mvp

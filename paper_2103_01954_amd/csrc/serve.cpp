@@ -187,7 +187,7 @@ void Server::start_locked(Slot &slot, uint64_t t, std::unique_lock<std::mutex> &
   if (st == MVP_OK) {
     slot.accel = a;
     hipError_t e = launch_zero_u64((uint64_t *)a->counters, 2, slot.stream);
-    if (e == hipSuccess) e = launch_march_fwd(a->view(prims.M), prims, req.rgba_out, nullptr, a->counters, slot.stream);
+    if (e == hipSuccess) e = launch_march_fwd(a->view(prims.M), prims, nullptr, req.rgba_out, nullptr, a->counters, slot.stream);
     if (e == hipSuccess) e = hipLaunchHostFunc(slot.stream, &Server::host_done, &slot);
     if (e != hipSuccess) {
       set_error("launch failed: %s", hipGetErrorString(e));

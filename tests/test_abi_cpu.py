@@ -40,3 +40,12 @@ def test_version_and_error_strings_need_no_device():
     assert lib.mvp_destroy(None) == _lib.MVP_ERR_INVALID
     assert b"NULL" in lib.mvp_last_error()
     assert lib.mvp_build_accel(None, None, None, 0, None, ctypes.byref(h), None) == _lib.MVP_ERR_INVALID
+
+
+def test_timing_entry_points_reject_bad_arguments_without_a_device():
+    lib = _lib.load()
+    ms = (ctypes.c_float * 4)()
+    n = ctypes.c_int32()
+    assert lib.mvp_timing_start(None, 4) == _lib.MVP_ERR_INVALID
+    assert lib.mvp_timing_read(None, 0, ms, ctypes.byref(n)) == _lib.MVP_ERR_INVALID
+    assert lib.mvp_timing_stop(None) == _lib.MVP_ERR_INVALID

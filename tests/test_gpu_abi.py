@@ -102,3 +102,22 @@ def test_repeated_builds_recycle_memory(mvp_ctx):
         acc.render_fwd(dp)
         acc.destroy()
     torch.cuda.synchronize()
+
+
+def test_kernel_timing_records_each_launch(mvp_ctx):
+    w, dp = _setup(mvp_ctx)
+    mvp_ctx.timing_start(2)
+    try:
+        for _ in range(3):        # the third launch of each kernel exceeds the capacity
+            acc = mvp_ctx.build_accel(dp, w.cams, w.params)
+            rgba, aux = acc.render_fwd(dp)
+            acc.render_bwd(dp, aux, torch.ones_like(rgba))
+            acc.destroy()
+        fwd, bwd = mvp_ctx.timing_read("fwd"), mvp_ctx.timing_read("bwd")
+    finally:
+        mvp_ctx.timing_stop()
+    assert len(fwd) == 2 and len(bwd) == 2
+    assert all(0.0 < t < 1000.0 for t in fwd + bwd)
+    ms = (C.c_float * 2)()
+    n = C.c_int32()
+    assert mvp_ctx.lib.mvp_timing_read(mvp_ctx.handle, 7, ms, C.byref(n)) == L.MVP_ERR_INVALID
