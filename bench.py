@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving latency run")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests per offered load")
-    ap.add_argument("--cpu-rows", type=int, default=16)
+    ap.add_argument("--cpu-rows", type=int, default=32)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB (reference for "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE scaling)")
@@ -155,6 +155,9 @@ def main():
         if ev: ev[3].record(stream)
         return acc
 
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     for _ in range(a.warmup):
         step().destroy()
     torch.cuda.synchronize()
@@ -174,6 +177,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop) / a.steps
+    note(f"{a.steps} timed steps: {start.elapsed_time(stop) / a.steps:.3f} ms per step")
     ray_s, prim_s = last.counts()
     info = last.info()
     last.destroy()
@@ -222,7 +226,21 @@ def main():
     serving = None
     if not a.no_serve:
         from paper_2103_01954_amd import serve
+        note("serving: 32 GiB budget")
         serving = serve.poisson_benchmark(ctx, n_requests=a.serve_requests, seed=5)
+        note("serving: 4 GiB budget")
+        # the same request stream on a 4 GiB device budget (1.1 GiB of it resident
+        # scenes): a 1920x1080 view of a 16384-primitive scene needs ~1.4 GB of
+        # pair lists, so admission by memory makes requests wait for scratch
+        small = Context(0)
+        try:
+            q = serve.poisson_benchmark(small, n_requests=max(a.serve_requests // 4, 50), seed=5, loads=(0.8,),
+                                        budget_bytes=4 << 30)
+        finally:
+            small.close()
+        serving["budget_4gib"] = {k: q[k] for k in ("capacity_fps", "p50_ms", "p99_ms", "failed")}
+    if not a.no_cpu:
+        note("oracle baseline on the host cores")
     cpu = None if a.no_cpu else cpu_baseline(a.size, a.views, a.cpu_rows)
 
     line = {

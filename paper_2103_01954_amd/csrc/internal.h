@@ -85,6 +85,25 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 }
 __host__ __device__ __forceinline__ int xcd_grid(int n) { return kXcd * ((n + kXcd - 1) / kXcd); }
 
+// Position s of the schedule -> tile index (v*T + ty*tiles_x + tx), visiting
+// each view in blocks of kTileBlock x kTileBlock tiles (row-major blocks,
+// row-major inside a block; edge blocks are cut to the grid).  The workgroups
+// resident on one XCD at a time then cover a compact patch of the screen, whose
+// primitives fit its L2 far better than a full-width stripe.
+constexpr int kTileBlock = 8;
+__device__ __forceinline__ int blocked_tile(int s, int tiles_x, int tiles_y) {
+  const int T = tiles_x * tiles_y;
+  const int v = s / T;
+  const int r = s - v * T;
+  const int by = r / (kTileBlock * tiles_x);
+  const int rr = r - by * kTileBlock * tiles_x;
+  const int hb = min(kTileBlock, tiles_y - by * kTileBlock);
+  const int bx = rr / (kTileBlock * hb);
+  const int q = rr - bx * kTileBlock * hb;
+  const int wb = min(kTileBlock, tiles_x - bx * kTileBlock);
+  return v * T + (by * kTileBlock + q / wb) * tiles_x + bx * kTileBlock + q % wb;
+}
+
 // Ray of thread t of the workgroup of `tile`: its slot, view and pixel.
 // Returns false if the thread has no ray.
 __device__ __forceinline__ bool tile_ray(const AccelView &av, int tile, int t, size_t *slot, int *v,

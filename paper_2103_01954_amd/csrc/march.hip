@@ -384,8 +384,9 @@ __global__ __launch_bounds__(kTileThreads) void k_march_fwd(AccelView av, const 
   __shared__ int s_list[kTileThreads];
   __shared__ int s_wave[kTileThreads / kWave];
   extern __shared__ float s_fade[];   // [M] when FADE
-  const int tile = xcd_tile(blockIdx.x, av.V * av.tiles_x * av.tiles_y);
-  if (tile < 0) return;
+  const int slot = xcd_tile(blockIdx.x, av.V * av.tiles_x * av.tiles_y);
+  if (slot < 0) return;
+  const int tile = blocked_tile(slot, av.tiles_x, av.tiles_y);
   if (FADE) fill_fade(s_fade, av.M, av.fade_alpha, av.fade_beta);   // visible after compact_tile's barrier
   int total;
   {
@@ -528,25 +529,70 @@ struct BwdOut {
   float *pay, *pos, *rot, *scale;
 };
 
-// Add the 32 register-accumulated corner gradients of one cell: into the LDS
-// copy of the primitive's gradient (LDS_ACC) or straight into device memory.
-// With the fade window the opacity gradient of a stored voxel is the window
-// times the gradient of its windowed value.
+// Culling-list entries per backward work item, and how a work item's pairs
+// are dealt to its threads.
+constexpr int kItemEntries = 64;
+constexpr bool kChunkedPairs = true;
+// Gradient flushes: rotate the corner order per lane, and keep the 4 corners
+// shared by consecutive cells in registers when a ray crosses one face.
+constexpr bool kRotateFlush = true;
+constexpr bool kShareFace = true;
+
+// The LDS copy of a primitive's payload gradient is planar, channel ch of voxel
+// v at ch * lds_plane(M) + v, with one word of padding per plane: lanes adding
+// the same corner and channel of different cells then spread over all 32 LDS
+// banks (the [voxel][channel] order of device memory would put them on 8).
+__host__ __device__ __forceinline__ size_t lds_plane(int M) { return (size_t)M * M * M + 1; }
+
+// Add the register-accumulated gradients of the corners of one cell selected by
+// `corners` (bit q = corner q = dx + 2 dy + 4 dz): into the LDS copy of the
+// primitive's gradient (LDS_ACC, planar) or straight into device memory
+// ([voxel][channel]).  With the fade window the opacity gradient of a stored
+// voxel is the window times the gradient of its windowed value.  Into LDS, lane
+// L visits the corners in the order q ^ (L mod 8): lanes of one wave that
+// flush the same cell then add to different voxels in each instruction instead
+// of serialising on one address.
 template <bool LDS_ACC, bool FADE>
 __device__ __forceinline__ void flush_cell(float *dst, size_t cell, int M, const float (&acc)[8][4],
-                                           const float (&wq)[8]) {
+                                           const float (&wq)[8], unsigned corners) {
   const size_t MM = (size_t)M * M;
-  const size_t off[8] = {0, 1, (size_t)M, (size_t)M + 1, MM, MM + 1, MM + M, MM + M + 1};
+  float v[8][4];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    float *p = dst + (cell + off[q]) * 4;
+    v[q][0] = acc[q][0];
+    v[q][1] = acc[q][1];
+    v[q][2] = acc[q][2];
+    v[q][3] = FADE ? acc[q][3] * wq[q] : acc[q][3];
+  }
+  const unsigned m = (LDS_ACC && kRotateFlush) ? (threadIdx.x & 7u) : 0u;
+  if (LDS_ACC && kRotateFlush) {   // v[q] <- v[q ^ m], one butterfly stage per bit of m
+#pragma unroll
+    for (int b = 1; b < 8; b <<= 1) {
+      const bool sw = (m & (unsigned)b) != 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (q & b) continue;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+          const float lo = v[q][ch], hi = v[q | b][ch];
+          v[q][ch] = sw ? hi : lo;
+          v[q | b][ch] = sw ? lo : hi;
+        }
+      }
+    }
+  }
+  const size_t plane = lds_plane(M);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const unsigned r = (unsigned)q ^ m;        // the corner held in v[q]
+    if (!((corners >> r) & 1u)) continue;
+    const size_t vox = cell + (r & 1u) + ((r >> 1) & 1u) * (size_t)M + (r >> 2) * MM;
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) {
-      const float x = (FADE && ch == 3) ? acc[q][ch] * wq[q] : acc[q][ch];
       if (LDS_ACC)
-        atomicAdd(p + ch, x);
+        atomicAdd(dst + ch * plane + vox, v[q][ch]);
       else
-        unsafeAtomicAdd(p + ch, x);
+        unsafeAtomicAdd(dst + vox * 4 + ch, v[q][ch]);
     }
   }
 }
@@ -580,74 +626,113 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
   const int jh = min(jr.y, ax.j_end);
   const size_t kb = (size_t)k * M3;
   float G0 = 0.f, G1 = 0.f, G2 = 0.f, H0 = 0.f, H1 = 0.f, H2 = 0.f;
-  int cur = -1;
   float4 cv[8];
   float acc[8][4];
   float wq[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) wq[q] = 1.0f;
-  for (int j = jr.x; j <= jh; ++j) {
-    const float tau = (float)j * dt;
-    const Cell c = locate(A, B, tau, M, hM);
-    if (c.idx != cur) {
-      if (cur >= 0 && gdst) flush_cell<LDS_ACC, FADE>(gdst, cur, M, acc, wq);
-      load_corners<BF16>(pay, kb + c.idx, M, cv);
-      if (FADE) {
-        corner_fade(s_fade, c, wq);
+  // One iteration per run of consecutive samples inside one voxel cell: the
+  // corner loads before the run and the flush after it are executed by the
+  // wave's lanes together (a per-sample "cell changed" branch would issue them
+  // once per lane, with the other lanes masked off).
+  int j = jr.x;
+  Cell c;
+  if (j <= jh) c = locate(A, B, (float)j * dt, M, hM);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) cv[q].w *= wq[q];
+  for (int q = 0; q < 8; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
+  while (j <= jh) {
+    const int cell = c.idx;
+    const int ci0 = c.i[0], ci1 = c.i[1], ci2 = c.i[2];
+    load_corners<BF16>(pay, kb + cell, M, cv);
+    if (FADE) {
+      corner_fade(s_fade, c, wq);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) cv[q].w *= wq[q];
+    }
+    do {
+      const float tau = (float)j * dt;
+      const float fx = c.f[0], fy = c.f[1], fz = c.f[2];
+      const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
+      float w[8];
+  #pragma unroll
+      for (int q = 0; q < 8; ++q) w[q] = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
+      float r = 0.f, gg = 0.f, b = 0.f, sg = 0.f;
+  #pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        r = fmaf(w[q], cv[q].x, r);
+        gg = fmaf(w[q], cv[q].y, gg);
+        b = fmaf(w[q], cv[q].z, b);
+        sg = fmaf(w[q], cv[q].w, sg);
+      }
+      const float gc = g.x * r + g.y * gg + g.z * b;
+      float a3, ws;   // dL/dsigma and the factor of g in dL/d(rgb) for this prim-sample
+      if (clamped && j == ax.j_end && (!seq || k >= rcv.kstar)) {
+        a3 = seq ? 0.f : wsig * (gc + tdot);
+        ws = seq ? (k == rcv.kstar ? wsig : 0.f) : wsig * sg;
+      } else {
+        a3 = dt * (tdot + gc);
+        ws = dt * sg;
+      }
+      const float a0 = ws * g.x, a1 = ws * g.y, a2 = ws * g.z;
+      float sc[8];
+  #pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        acc[q][0] = fmaf(w[q], a0, acc[q][0]);
+        acc[q][1] = fmaf(w[q], a1, acc[q][1]);
+        acc[q][2] = fmaf(w[q], a2, acc[q][2]);
+        acc[q][3] = fmaf(w[q], a3, acc[q][3]);
+        sc[q] = a0 * cv[q].x + a1 * cv[q].y + a2 * cv[q].z + a3 * cv[q].w;
+      }
+      // gradient of the trilinear interpolant of sc with respect to y
+      const float gx = hM * (wy[0] * wz[0] * (sc[1] - sc[0]) + wy[1] * wz[0] * (sc[3] - sc[2]) +
+                             wy[0] * wz[1] * (sc[5] - sc[4]) + wy[1] * wz[1] * (sc[7] - sc[6]));
+      const float gyv = hM * (wx[0] * wz[0] * (sc[2] - sc[0]) + wx[1] * wz[0] * (sc[3] - sc[1]) +
+                              wx[0] * wz[1] * (sc[6] - sc[4]) + wx[1] * wz[1] * (sc[7] - sc[5]));
+      const float gz = hM * (wx[0] * wy[0] * (sc[4] - sc[0]) + wx[1] * wy[0] * (sc[5] - sc[1]) +
+                             wx[0] * wy[1] * (sc[6] - sc[2]) + wx[1] * wy[1] * (sc[7] - sc[3]));
+      G0 += gx;
+      G1 += gyv;
+      G2 += gz;
+      H0 = fmaf(tau, gx, H0);
+      H1 = fmaf(tau, gyv, H1);
+      H2 = fmaf(tau, gz, H2);
+      ++j;
+      if (j > jh) break;
+      c = locate(A, B, (float)j * dt, M, hM);
+    } while (c.idx == cell);
+    // the next run's cell (if any) is c: when it is the neighbour across one
+    // face, the 4 corners on that face carry over and only the other 4 flush
+    const int dx = c.i[0] - ci0, dy = c.i[1] - ci1, dz = c.i[2] - ci2;
+    const bool face = kShareFace && j <= jh && abs(dx) + abs(dy) + abs(dz) == 1;
+    const int bit = dx ? 1 : (dy ? 2 : 4);
+    const bool up = dx + dy + dz > 0;
+    // slot q is left behind (flushed) and refilled from slot q ^ bit iff
+    // ((q & bit) != 0) == !up; the other slots move out and start at zero
+    unsigned behind = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (((q & bit) != 0) == !up) behind |= 1u << q;
+    if (gdst) flush_cell<LDS_ACC, FADE>(gdst, cell, M, acc, wq, face ? behind : 0xffu);
+    if (face) {
+      float nv[8][4];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const bool refill = (behind >> q) & 1u;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+          const float partner = bit == 1 ? acc[q ^ 1][ch] : (bit == 2 ? acc[q ^ 2][ch] : acc[q ^ 4][ch]);
+          nv[q][ch] = refill ? partner : 0.f;
+        }
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
-      cur = c.idx;
-    }
-    const float fx = c.f[0], fy = c.f[1], fz = c.f[2];
-    const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
-    float w[8];
+      for (int q = 0; q < 8; ++q)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) w[q] = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
-    float r = 0.f, gg = 0.f, b = 0.f, sg = 0.f;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      r = fmaf(w[q], cv[q].x, r);
-      gg = fmaf(w[q], cv[q].y, gg);
-      b = fmaf(w[q], cv[q].z, b);
-      sg = fmaf(w[q], cv[q].w, sg);
-    }
-    const float gc = g.x * r + g.y * gg + g.z * b;
-    float a3, ws;   // dL/dsigma and the factor of g in dL/d(rgb) for this prim-sample
-    if (clamped && j == ax.j_end && (!seq || k >= rcv.kstar)) {
-      a3 = seq ? 0.f : wsig * (gc + tdot);
-      ws = seq ? (k == rcv.kstar ? wsig : 0.f) : wsig * sg;
+        for (int ch = 0; ch < 4; ++ch) acc[q][ch] = nv[q][ch];
     } else {
-      a3 = dt * (tdot + gc);
-      ws = dt * sg;
-    }
-    const float a0 = ws * g.x, a1 = ws * g.y, a2 = ws * g.z;
-    float sc[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      acc[q][0] = fmaf(w[q], a0, acc[q][0]);
-      acc[q][1] = fmaf(w[q], a1, acc[q][1]);
-      acc[q][2] = fmaf(w[q], a2, acc[q][2]);
-      acc[q][3] = fmaf(w[q], a3, acc[q][3]);
-      sc[q] = a0 * cv[q].x + a1 * cv[q].y + a2 * cv[q].z + a3 * cv[q].w;
+      for (int q = 0; q < 8; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
     }
-    // gradient of the trilinear interpolant of sc with respect to y
-    const float gx = hM * (wy[0] * wz[0] * (sc[1] - sc[0]) + wy[1] * wz[0] * (sc[3] - sc[2]) +
-                           wy[0] * wz[1] * (sc[5] - sc[4]) + wy[1] * wz[1] * (sc[7] - sc[6]));
-    const float gyv = hM * (wx[0] * wz[0] * (sc[2] - sc[0]) + wx[1] * wz[0] * (sc[3] - sc[1]) +
-                            wx[0] * wz[1] * (sc[6] - sc[4]) + wx[1] * wz[1] * (sc[7] - sc[5]));
-    const float gz = hM * (wx[0] * wy[0] * (sc[4] - sc[0]) + wx[1] * wy[0] * (sc[5] - sc[1]) +
-                           wx[0] * wy[1] * (sc[6] - sc[2]) + wx[1] * wy[1] * (sc[7] - sc[3]));
-    G0 += gx;
-    G1 += gyv;
-    G2 += gz;
-    H0 = fmaf(tau, gx, H0);
-    H1 = fmaf(tau, gyv, H1);
-    H2 = fmaf(tau, gz, H2);
   }
-  if (cur >= 0 && gdst) flush_cell<LDS_ACC, FADE>(gdst, cur, M, acc, wq);
   if (!pose) return;
   // y = A (o + tau d - t), A = diag(1/s) R^T; d is the unit pixel ray
   int rv, px, py;
@@ -688,8 +773,7 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
   }
 }
 
-// Culling-list entries per backward work item.
-constexpr int kItemEntries = 64;
+
 
 // Backward, one workgroup per work item: up to kItemEntries culling-list
 // entries (tile, primitive k) of one primitive.  The pairs of those entries
@@ -711,11 +795,12 @@ __global__ __launch_bounds__(kTileThreads) void k_bwd_items(AccelView av, const 
   __shared__ int s_prim;
   const int M = av.M;
   const size_t M3 = (size_t)M * M * M;
-  const int nacc = (int)(M3 * 4);
+  const int nacc = (int)(M3 * 4);                 // gradient values of one primitive
+  const int nlds = (int)(lds_plane(M) * 4);       // their planar LDS copy
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const bool pose = out.pos || out.rot || out.scale;
   float *s_grad = s_dyn;
-  float *s_fade = s_dyn + ((LDS_ACC && out.pay) ? nacc : 0);
+  float *s_fade = s_dyn + ((LDS_ACC && out.pay) ? nlds : 0);
   if (FADE) {
     fill_fade(s_fade, M, av.fade_alpha, av.fade_beta);
     __syncthreads();
@@ -752,21 +837,32 @@ __global__ __launch_bounds__(kTileThreads) void k_bwd_items(AccelView av, const 
       if (lane < kItemEntries) s_pre[lane + 1] = incl;
     }
     if (LDS_ACC && out.pay)
-      for (int i = threadIdx.x; i < nacc; i += kTileThreads) s_grad[i] = 0.f;
+      for (int i = threadIdx.x; i < nlds; i += kTileThreads) s_grad[i] = 0.f;
     __syncthreads();
     const uint32_t total = s_pre[nent];
     float *gdst = out.pay ? (LDS_ACC ? s_grad : out.pay + (size_t)k * M3 * 4) : nullptr;
     float P[15];
 #pragma unroll
     for (int i = 0; i < 15; ++i) P[i] = 0.f;
-    for (uint32_t i = threadIdx.x; i < total; i += kTileThreads) {
-      int lo = 0, hi = nent - 1;   // entry of flattened pair i: last q with s_pre[q] <= i
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_pre[mid] <= i) lo = mid; else hi = mid - 1;
+    // kChunkedPairs: each thread replays a contiguous run of the flattened
+    // pairs, so the lanes of a wave follow rays some pixels apart, which flush
+    // into different voxel cells at once; otherwise pair i goes to thread
+    // i mod 256 (neighbouring pixels on neighbouring lanes).
+    const uint32_t per = kChunkedPairs ? (total + kTileThreads - 1) / kTileThreads : 1;
+    const uint32_t stride = kChunkedPairs ? 1 : kTileThreads;
+    uint32_t i = kChunkedPairs ? threadIdx.x * per : threadIdx.x;
+    const uint32_t iend = kChunkedPairs ? min(total, i + per) : total;
+    if (i < iend) {
+      int q = 0, hi = nent - 1;    // entry of flattened pair i: last q with s_pre[q] <= i
+      while (q < hi) {
+        const int mid = (q + hi + 1) >> 1;
+        if (s_pre[mid] <= i) q = mid; else hi = mid - 1;
       }
-      const uint32_t e = av.entry_pairs[s_start[lo] + (i - s_pre[lo])];
-      bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, e, k, gdst, s_fade, pose, P);
+      for (; i < iend; i += stride) {
+        while (s_pre[q + 1] <= i) ++q;
+        const uint32_t e = av.entry_pairs[s_start[q] + (i - s_pre[q])];
+        bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, e, k, gdst, s_fade, pose, P);
+      }
     }
     if (pose) {
 #pragma unroll
@@ -793,8 +889,9 @@ __global__ __launch_bounds__(kTileThreads) void k_bwd_items(AccelView av, const 
     }
     if (LDS_ACC && out.pay && total > 0) {
       float *dst = out.pay + M3 * 4 * (size_t)k;
-      for (int i = threadIdx.x; i < nacc; i += kTileThreads) {
-        const float x = s_grad[i];
+      const size_t plane = lds_plane(M);
+      for (int i = threadIdx.x; i < nacc; i += kTileThreads) {   // device order: voxel i/4, channel i%4
+        const float x = s_grad[(i & 3) * plane + (i >> 2)];
         if (x != 0.f) unsafeAtomicAdd(dst + i, x);
       }
     }
@@ -802,8 +899,9 @@ __global__ __launch_bounds__(kTileThreads) void k_bwd_items(AccelView av, const 
   }
 }
 
-// Largest per-primitive gradient (M^3 x 4 floats) accumulated in LDS.
-constexpr size_t kLdsGradBytes = 64 * 1024;
+// Largest planar LDS copy of a primitive's gradient (4 planes of M^3 + 1
+// floats): up to M = 16.
+constexpr size_t kLdsGradBytes = 64 * 1024 + 16;
 
 hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_items_max,
                             const mvp_ray_aux *aux, const float *grad_rgba, const float *bg,
@@ -827,7 +925,7 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || p.n_prim == 0 || n_items_max == 0) return e;
   const size_t M3 = (size_t)p.M * p.M * p.M;
-  const size_t lds = M3 * 16;
+  const size_t lds = lds_plane(p.M) * 16;
   bool in_lds = lds <= kLdsGradBytes;
   if (in_lds && g_pay) {
     // allow more than the default dynamic LDS per workgroup (gfx950 has 160 KB)
