@@ -362,9 +362,10 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   MVP_HIP(launch_zero_u32(prim_cnt, (size_t)N, s));
   MVP_HIP(launch_prim_entry_fill(a->tile_list, n_tile_pairs, a->prim_entry_off, prim_cnt, a->prim_entries, s));
   MVP_HIP(launch_segment_sort(a->prim_entry_off, a->prim_entries, (int64_t)N, s));
-  MVP_HIP(launch_item_count(a->prim_entry_off, N, backward_item_entries(), prim_cnt, s));
+  a->item_entries = backward_item_entries(prims->M);
+  MVP_HIP(launch_item_count(a->prim_entry_off, N, a->item_entries, prim_cnt, s));
   MVP_HIP(launch_scan_u32_u64(prim_cnt, a->item_off, (size_t)N, scratch, s));
-  a->n_items_max = (int64_t)(n_tile_pairs / backward_item_entries()) + N;
+  a->n_items_max = (int64_t)(n_tile_pairs / a->item_entries) + N;
 
   // per-ray pair counts and per-entry counts, offsets
   MVP_HIP(launch_hit_count(av, 0, ray_cnt, entry_cnt, s));

@@ -83,6 +83,7 @@ struct mvp_accel {
   uint32_t *prim_entries = nullptr;
   uint64_t *item_off = nullptr;
   int64_t n_items_max = 0;             // upper bound on the backward work items
+  int32_t item_entries = 64;           // culling-list entries per backward work item
   uint64_t *entry_off = nullptr;
   uint32_t *entry_pairs = nullptr;
   uint64_t *ray_off = nullptr;
@@ -104,6 +105,7 @@ struct mvp_accel {
     v.fade_alpha = params.fade_alpha; v.fade_beta = params.fade_beta; v.combine = params.combine;
     v.cams = cams; v.xf = xf; v.tile_off = tile_off; v.tile_list = tile_list;
     v.prim_entry_off = prim_entry_off; v.prim_entries = prim_entries; v.item_off = item_off;
+    v.item_entries = item_entries;
     v.entry_off = entry_off; v.entry_pairs = entry_pairs;
     v.ray_off = ray_off; v.pa = pa; v.pb = pb; v.pj = pj;
     v.n_slots = n_slots; v.ray_pix = ray_pix; v.tile_ray_off = tile_ray_off; v.tile_rays = tile_rays;

@@ -29,7 +29,7 @@ struct DevCam {
 // tile_off[t+1]), primitive ids in increasing order.  Transposed: primitive k
 // owns the list entries prim_entries[prim_entry_off[k] .. prim_entry_off[k+1])
 // (ascending), grouped into backward work items item_off[k] .. item_off[k+1]
-// of at most kItemEntries entries each.
+// of at most item_entries entries each.
 // Pairs: ray r owns pairs [ray_off[r], ray_off[r+1]) sorted by (jlo, id);
 // pair i is (pa[i] = (a, primitive id), pb[i] = (b, ray index),
 // pj[i] = (jlo, jhi)): local ray y(t) = a + t b and its sample interval.
@@ -49,6 +49,7 @@ struct AccelView {
   float step, eps, t_near;
   float fade_alpha, fade_beta; // opacity fade window (alpha == 0: none)
   int32_t combine;             // 0: sum rule, 1: sequential in primitive-id order
+  int32_t item_entries;        // culling-list entries per backward work item
   const DevCam *cams;          // [V]
   const float4 *xf;            // [N*3]: rows of A = diag(1/s) R^T, .w = t
   const uint64_t *tile_off;    // [V*T+1]
@@ -158,7 +159,7 @@ hipError_t launch_prim_entry_fill(const uint32_t *tile_list, uint64_t n, const u
                                   uint32_t *prim_entries, hipStream_t s);
 hipError_t launch_item_count(const uint64_t *prim_entry_off, int n_prim, int per_item, uint32_t *cnt,
                              hipStream_t s);
-int backward_item_entries();
+int backward_item_entries(int M);   // culling-list entries per backward work item (<= 64)
 // sort each segment [off[i], off[i+1]) of data (n_seg segments) ascending
 hipError_t launch_segment_sort(const uint64_t *off, uint32_t *data, int64_t n_seg, hipStream_t s);
 // ray subsets: count the sampled rays of every tile (flag: 1 = pixel id out of

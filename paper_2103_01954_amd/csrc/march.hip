@@ -42,6 +42,16 @@
 
 namespace mvp {
 
+// Largest number of culling-list entries per backward work item (the build
+// picks the number per structure, see backward_item_entries), and how a work
+// item's pairs are dealt to its threads.
+constexpr int kItemEntries = 64;
+constexpr bool kChunkedPairs = true;
+// Gradient flushes rotate the corner order per lane, and keep the 4 corners
+// shared by consecutive cells in registers when a ray crosses one face.
+constexpr bool kRotateFlush = true;
+constexpr bool kShareFace = true;
+
 template <bool BF16>
 struct Voxels;
 
@@ -529,14 +539,6 @@ struct BwdOut {
   float *pay, *pos, *rot, *scale;
 };
 
-// Culling-list entries per backward work item, and how a work item's pairs
-// are dealt to its threads.
-constexpr int kItemEntries = 64;
-constexpr bool kChunkedPairs = true;
-// Gradient flushes: rotate the corner order per lane, and keep the 4 corners
-// shared by consecutive cells in registers when a ray crosses one face.
-constexpr bool kRotateFlush = true;
-constexpr bool kShareFace = true;
 
 // The LDS copy of a primitive's payload gradient is planar, channel ch of voxel
 // v at ch * lds_plane(M) + v, with one word of padding per plane: lanes adding
@@ -713,7 +715,7 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
     for (int q = 0; q < 8; ++q)
       if (((q & bit) != 0) == !up) behind |= 1u << q;
     if (gdst) flush_cell<LDS_ACC, FADE>(gdst, cell, M, acc, wq, face ? behind : 0xffu);
-    if (face) {
+    if (face && gdst) {
       float nv[8][4];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -818,8 +820,8 @@ __global__ __launch_bounds__(kTileThreads) void k_bwd_items(AccelView av, const 
     __syncthreads();
     const int k = s_prim;
     const uint64_t chunk = it - av.item_off[k];
-    const uint64_t eb = av.prim_entry_off[k] + chunk * kItemEntries;
-    const int nent = (int)min<uint64_t>(kItemEntries, av.prim_entry_off[k + 1] - eb);
+    const uint64_t eb = av.prim_entry_off[k] + chunk * (uint64_t)av.item_entries;
+    const int nent = (int)min<uint64_t>((uint64_t)av.item_entries, av.prim_entry_off[k + 1] - eb);
     if (wave == 0) {          // the entries' pair ranges and their prefix sums
       uint32_t cnt = 0;
       if (lane < nent) {
@@ -924,7 +926,6 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
 #undef MVP_RAYS
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || p.n_prim == 0 || n_items_max == 0) return e;
-  const size_t M3 = (size_t)p.M * p.M * p.M;
   const size_t lds = lds_plane(p.M) * 16;
   bool in_lds = lds <= kLdsGradBytes;
   if (in_lds && g_pay) {
@@ -956,6 +957,9 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   return e;
 }
 
-int backward_item_entries() { return kItemEntries; }
+// Entries per backward work item: 8^3 payloads flush small gradients, so
+// shorter items (more of them) balance better; larger payloads amortise the
+// per-item zeroing and flush of their LDS gradient over 64 entries.
+int backward_item_entries(int M) { return M <= 8 ? 32 : kItemEntries; }
 
 }  // namespace mvp
