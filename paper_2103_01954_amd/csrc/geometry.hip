@@ -644,14 +644,17 @@ hipError_t launch_hit_count(const AccelView &av, int mode, uint32_t *ray_cnt, ui
 // primitive-id order.  Pass 2 ranks each pair by (jlo, list position), the
 // order the forward marches them in: in LDS for lists of at most kKeys pairs
 // (jlo < 2^24 in the low 24 bits, the rank in the top 8), in device memory
-// (tkey/trank) for longer ones.  Pass 3 repeats the slab tests and writes
-// every pair straight to its ranked slot of the ray's segment
-// [ray_off[ray], ray_off[ray+1]):
+// (tkey/trank) for longer ones.  Pass 3 writes every pair to its ranked slot of
+// the ray's segment [ray_off[ray], ray_off[ray+1]):
 //   pa = (a, primitive id), pb = (b, ray index), pj = (jlo, jhi),
 // and lists it under its culling-list entry (entry_pairs[entry_off[g] ..],
-// pixel order) for the backward.  Mode 1 writes only the primitive ids of the
-// slab hits into `ids`, in primitive-id order.
-constexpr int kKeys = 48;
+// pixel order) for the backward.  When the whole culling list fits one LDS
+// chunk (the common case) it stays staged, and a ray with a short list
+// recomputes its pairs in rank order and writes its segment front to back, so
+// each output line is completed in one burst instead of piece by piece.  Mode
+// 1 writes only the primitive ids of the slab hits into `ids`, in primitive-id
+// order.
+constexpr int kKeys = 32;
 
 __global__ __launch_bounds__(kTileThreads) void k_hit_emit(AccelView av, int mode, int32_t *__restrict__ tkey,
                                                             uint32_t *__restrict__ trank, float4 *__restrict__ pa,
@@ -662,6 +665,8 @@ __global__ __launch_bounds__(kTileThreads) void k_hit_emit(AccelView av, int mod
   __shared__ uint32_t s_bits[kStage / 32][kTileThreads];
   __shared__ uint32_t s_cnt[kTileThreads / kWave][kStage];
   __shared__ uint32_t s_key[kKeys][kTileThreads];
+  __shared__ uint8_t s_ent[kKeys][kTileThreads];   // single-chunk lists: entry of the i-th pair
+  __shared__ uint8_t s_inv[kKeys][kTileThreads];   // ... and of the pair of rank r
   const int tile = blockIdx.x;
   const int t = threadIdx.x;
   int v, px, py;
@@ -675,6 +680,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hit_emit(AccelView av, int mod
   const int n = valid ? (int)(av.ray_off[ray + 1] - out0) : 0;   // same predicate as the count pass
   const bool in_lds = n <= kKeys;
   const uint64_t lb = av.tile_off[tile], le = av.tile_off[tile + 1];
+  const bool single = le - lb <= (uint64_t)kStage;                 // the same for the whole workgroup
   const unsigned long long lt = (1ull << lane) - 1ull;
   // pass 1: first samples (or, in mode 1, primitive ids) in list order
   int i = 0;
@@ -683,17 +689,25 @@ __global__ __launch_bounds__(kTileThreads) void k_hit_emit(AccelView av, int mod
     __syncthreads();
     stage_chunk(sm, av, cam, c0, nc);
     __syncthreads();
+    uint32_t word = 0;
     for (int e = 0; e < nc; ++e) {
       float a[3], b[3];
       int jlo = 0, jhi = 0;
       if (i < n && pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi)) {
-        if (mode != 0)
+        if (mode != 0) {
           ids[out0 + i] = sm.id[e];
-        else if (in_lds)
+        } else if (in_lds) {
           s_key[i][t] = (uint32_t)jlo;
-        else
+          s_ent[i][t] = (uint8_t)e;
+        } else {
           tkey[out0 + i] = jlo;
+        }
         ++i;
+        word |= 1u << (e & 31);
+      }
+      if (single && ((e & 31) == 31 || e == nc - 1)) {
+        s_bits[e >> 5][t] = word;
+        word = 0;
       }
     }
   }
@@ -714,10 +728,12 @@ __global__ __launch_bounds__(kTileThreads) void k_hit_emit(AccelView av, int mod
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       if (i0 + q < n) {
-        if (in_lds)
+        if (in_lds) {
           s_key[i0 + q][t] = (uint32_t)key[q] | ((uint32_t)rank[q] << 24);
-        else
+          s_inv[rank[q]][t] = s_ent[i0 + q][t];
+        } else {
           trank[out0 + i0 + q] = (uint32_t)rank[q];
+        }
       }
     }
   }
@@ -725,25 +741,42 @@ __global__ __launch_bounds__(kTileThreads) void k_hit_emit(AccelView av, int mod
   i = 0;
   for (uint64_t c0 = lb; c0 < le; c0 += kStage) {
     const int nc = (int)min<uint64_t>(kStage, le - c0);
-    __syncthreads();
-    stage_chunk(sm, av, cam, c0, nc);
-    __syncthreads();
+    if (!single) {
+      __syncthreads();
+      stage_chunk(sm, av, cam, c0, nc);
+      __syncthreads();
+    }
     const int ic = i;
-    uint32_t word = 0;
-    for (int e = 0; e < nc; ++e) {
-      float a[3], b[3];
-      int jlo = 0, jhi = 0;
-      if (i < n && pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi)) {
-        const uint64_t dst = out0 + (in_lds ? (s_key[i][t] >> 24) : trank[out0 + i]);
+    if (single && in_lds) {
+      // the list is still staged: recompute the pairs in rank order
+      for (int r = 0; r < n; ++r) {
+        const int e = s_inv[r][t];
+        float a[3], b[3];
+        int jlo = 0, jhi = 0;
+        (void)pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi);
+        const uint64_t dst = out0 + r;
         pa[dst] = make_float4(a[0], a[1], a[2], __int_as_float(sm.id[e]));
         pb[dst] = make_float4(b[0], b[1], b[2], __int_as_float((int)ray));
         pj[dst] = make_int2(jlo, jhi);
-        ++i;
-        word |= 1u << (e & 31);
       }
-      if ((e & 31) == 31 || e == nc - 1) {
-        s_bits[e >> 5][t] = word;
-        word = 0;
+      i = n;
+    } else {
+      uint32_t word = 0;
+      for (int e = 0; e < nc; ++e) {
+        float a[3], b[3];
+        int jlo = 0, jhi = 0;
+        if (i < n && pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi)) {
+          const uint64_t dst = out0 + (in_lds ? (s_key[i][t] >> 24) : trank[out0 + i]);
+          pa[dst] = make_float4(a[0], a[1], a[2], __int_as_float(sm.id[e]));
+          pb[dst] = make_float4(b[0], b[1], b[2], __int_as_float((int)ray));
+          pj[dst] = make_int2(jlo, jhi);
+          ++i;
+          word |= 1u << (e & 31);
+        }
+        if (!single && ((e & 31) == 31 || e == nc - 1)) {
+          s_bits[e >> 5][t] = word;
+          word = 0;
+        }
       }
     }
     for (int e = 0; e < nc; ++e) {
