@@ -310,7 +310,7 @@ __device__ bool seq_sample(const AccelView &av, const void *pay, const float *fa
 // The ray's pairs are sorted by (first sample, primitive id): a window visits
 // only the pairs that overlap it, and the primitives of one sample are summed
 // in primitive-id order.
-constexpr int kWin = 8;
+constexpr int kWin = 12;
 
 template <bool BF16, bool FADE>
 __device__ void march_ray(const AccelView &av, const void *pay, const float *fade, uint64_t beg, uint64_t end,
@@ -783,8 +783,13 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
 // the payload gradient of k is accumulated in LDS (LDS_ACC) and added to
 // device memory once per item, the pose gradient is reduced over the
 // workgroup and added with 15 atomics.
-template <bool BF16, bool LDS_ACC, bool FADE>
-__global__ __launch_bounds__(kTileThreads) void k_bwd_items(AccelView av, const float *__restrict__ rot,
+//
+// WAVES > 1 asks the compiler for that many waves per SIMD (it then keeps the
+// kernel within 512 / WAVES registers, spilling a few); it is used when the
+// LDS gradient leaves room for that many workgroups per CU.
+template <bool BF16, bool LDS_ACC, bool FADE, int WAVES>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_bwd_items(
+    AccelView av, const float *__restrict__ rot,
                                                              const float *__restrict__ scale,
                                                              const void *__restrict__ pay,
                                                              const mvp_ray_aux *__restrict__ aux,
@@ -928,10 +933,15 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   if (e != hipSuccess || p.n_prim == 0 || n_items_max == 0) return e;
   const size_t lds = lds_plane(p.M) * 16;
   bool in_lds = lds <= kLdsGradBytes;
+  // 3 waves per SIMD when 3 workgroups' LDS fits a CU (160 KB; ~1 KB static)
+  const bool w3 = !(in_lds && g_pay) || 3 * (lds + fade_shm + 1024) <= 160 * 1024;
   if (in_lds && g_pay) {
     // allow more than the default dynamic LDS per workgroup (gfx950 has 160 KB)
-    const void *fn = bf16 ? (fade ? (const void *)k_bwd_items<true, true, true> : (const void *)k_bwd_items<true, true, false>)
-                          : (fade ? (const void *)k_bwd_items<false, true, true> : (const void *)k_bwd_items<false, true, false>);
+    const void *fn =
+        bf16 ? (fade ? (w3 ? (const void *)k_bwd_items<true, true, true, 3> : (const void *)k_bwd_items<true, true, true, 1>)
+                     : (w3 ? (const void *)k_bwd_items<true, true, false, 3> : (const void *)k_bwd_items<true, true, false, 1>))
+             : (fade ? (w3 ? (const void *)k_bwd_items<false, true, true, 3> : (const void *)k_bwd_items<false, true, true, 1>)
+                     : (w3 ? (const void *)k_bwd_items<false, true, false, 3> : (const void *)k_bwd_items<false, true, false, 1>));
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsGradBytes + 4096)) != hipSuccess) {
       (void)hipGetLastError();
       in_lds = lds + fade_shm <= 48 * 1024;
@@ -941,9 +951,15 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   BwdOut out{g_pay, g_pos, g_rot, g_scale};
   const size_t shm = (in_lds && g_pay ? lds : 0) + fade_shm;
   if (t0) (void)hipEventRecord(t0, s);
-#define MVP_BWD(B, L, F)                                                                                  \
-  hipLaunchKernelGGL((k_bwd_items<B, L, F>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale,   \
-                     p.payload, aux, (const float4 *)grad_rgba, rc, out)
+#define MVP_BWD(B, L, F)                                                                                      \
+  do {                                                                                                        \
+    if (w3)                                                                                                   \
+      hipLaunchKernelGGL((k_bwd_items<B, L, F, 3>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale, \
+                         p.payload, aux, (const float4 *)grad_rgba, rc, out);                                 \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_bwd_items<B, L, F, 1>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale, \
+                         p.payload, aux, (const float4 *)grad_rgba, rc, out);                                 \
+  } while (0)
   if (bf16) {
     if (in_lds) { if (fade) MVP_BWD(true, true, true); else MVP_BWD(true, true, false); }
     else { if (fade) MVP_BWD(true, false, true); else MVP_BWD(true, false, false); }
