@@ -201,7 +201,9 @@ def main():
         except Exception:
             traffic = None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kern,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            # DRAM bytes per launch (rocprofv3, profiles/traffic.json) over the same kernel time
+            "traffic_gbs": round(traffic / (kms / 1e3) / 1e9, 1) if traffic else None, "kernel": kern,
             "kernel_ms": round(kms, 3), "bytes_per_prim_sample": per,
             "kernel_ms_each": {KERN_FWD: round(fwd_ms, 3), KERN_BWD: round(bwd_ms, 3)},
             "call_ms": {"render_fwd": round(fwd_call_ms, 3), "render_bwd": round(bwd_call_ms, 3)}}
