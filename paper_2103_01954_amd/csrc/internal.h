@@ -105,8 +105,9 @@ __device__ __forceinline__ int blocked_tile(int s, int tiles_x, int tiles_y) {
   return v * T + (by * kTileBlock + q / wb) * tiles_x + bx * kTileBlock + q % wb;
 }
 
-// Ray of thread t of the workgroup of `tile`: its slot, view and pixel.
-// Returns false if the thread has no ray.
+// Ray number t (0 <= t < 256, row-major in the 16x16 tile) of `tile`: its
+// slot, view and pixel.  Returns false if there is no such ray (a tile cut by
+// the image border, or a ray subset with fewer rays in the tile).
 __device__ __forceinline__ bool tile_ray(const AccelView &av, int tile, int t, size_t *slot, int *v,
                                          int *px, int *py) {
   const int T = av.tiles_x * av.tiles_y;
@@ -179,7 +180,7 @@ hipError_t launch_hit_emit(const AccelView &av, int mode, int32_t *tkey, uint32_
 // bg: optional background [rays,3] composited under the premultiplied colour
 hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, const float *bg, float *rgba,
                             mvp_ray_aux *aux, unsigned long long *counters, hipStream_t s);
-// backward; rc is scratch of 2 floats per ray; bg/rgba/g_bg for a composited forward
+// backward; rc is scratch of one RayConst per ray; bg/rgba/g_bg for a composited forward
 hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_items_max,
                             const mvp_ray_aux *aux, const float *grad_rgba, const float *bg,
                             const float *rgba, RayConst *rc, float *g_pay, float *g_pos, float *g_rot,

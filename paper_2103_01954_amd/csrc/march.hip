@@ -24,12 +24,12 @@
 // and for the sequential combine Tdot = -g . c_k*S, the primitives before k*
 // at S take the j < S formulas, dL/dc_k*S = (1 - T*) g with T* the opacity
 // just before k*, and dL/dsigma_k*S = 0.
-// The pairs are replayed one workgroup per (screen tile, primitive): channel
-// adjoints go to the 8 voxel corners with the trilinear weights, accumulated
-// in registers while consecutive samples stay in one cell and then in an LDS
-// copy of the primitive's gradient, which is added to device memory once per
-// workgroup; the pose gradient (through y = A (o + t d - pos)) is reduced over
-// the workgroup.
+// The pairs are replayed by work items, each up to 32 or 64 culling-list
+// entries (screen tile, primitive) of one primitive: channel adjoints go to
+// the 8 voxel corners with the trilinear weights, accumulated in registers
+// over a run of samples in one cell and then in an LDS copy of the
+// primitive's gradient, which is added to device memory once per item; the
+// pose gradient (through y = A (o + t d - pos)) is reduced over the workgroup.
 //
 // Built with -ffp-contract=off; fused multiply-adds are written explicitly.
 #include <hip/hip_runtime.h>
