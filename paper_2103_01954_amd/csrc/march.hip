@@ -651,47 +651,62 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
 #pragma unroll
       for (int q = 0; q < 8; ++q) cv[q].w *= wq[q];
     }
+    // the cell's field in the monomial basis: f = sum_q cf[q] m_q with
+    // m_q = product of the offsets (x, y, z) named by the bits of q
+    float cf[8][4];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      cf[q][0] = cv[q].x;
+      cf[q][1] = cv[q].y;
+      cf[q][2] = cv[q].z;
+      cf[q][3] = cv[q].w;
+    }
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q & bit)
+#pragma unroll
+          for (int ch = 0; ch < 4; ++ch) cf[q][ch] -= cf[q ^ bit][ch];
     do {
       const float tau = (float)j * dt;
       const float fx = c.f[0], fy = c.f[1], fz = c.f[2];
-      const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
-      float w[8];
-  #pragma unroll
-      for (int q = 0; q < 8; ++q) w[q] = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
-      float r = 0.f, gg = 0.f, b = 0.f, sg = 0.f;
-  #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        r = fmaf(w[q], cv[q].x, r);
-        gg = fmaf(w[q], cv[q].y, gg);
-        b = fmaf(w[q], cv[q].z, b);
-        sg = fmaf(w[q], cv[q].w, sg);
+      const float mxy = fx * fy, mxz = fx * fz, myz = fy * fz, mxyz = mxy * fz;
+      const float mq[8] = {1.0f, fx, fy, mxy, fz, mxz, myz, mxyz};
+      float val[4];
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        float v = cf[0][ch];
+#pragma unroll
+        for (int q = 1; q < 8; ++q) v = fmaf(mq[q], cf[q][ch], v);
+        val[ch] = v;
       }
-      const float gc = g.x * r + g.y * gg + g.z * b;
+      const float gc = g.x * val[0] + g.y * val[1] + g.z * val[2];
       float a3, ws;   // dL/dsigma and the factor of g in dL/d(rgb) for this prim-sample
       if (clamped && j == ax.j_end && (!seq || k >= rcv.kstar)) {
         a3 = seq ? 0.f : wsig * (gc + tdot);
-        ws = seq ? (k == rcv.kstar ? wsig : 0.f) : wsig * sg;
+        ws = seq ? (k == rcv.kstar ? wsig : 0.f) : wsig * val[3];
       } else {
         a3 = dt * (tdot + gc);
-        ws = dt * sg;
+        ws = dt * val[3];
       }
       const float a0 = ws * g.x, a1 = ws * g.y, a2 = ws * g.z;
-      float sc[8];
-  #pragma unroll
+      // adjoint of the monomial coefficients; the corners' are formed at the flush
+#pragma unroll
       for (int q = 0; q < 8; ++q) {
-        acc[q][0] = fmaf(w[q], a0, acc[q][0]);
-        acc[q][1] = fmaf(w[q], a1, acc[q][1]);
-        acc[q][2] = fmaf(w[q], a2, acc[q][2]);
-        acc[q][3] = fmaf(w[q], a3, acc[q][3]);
-        sc[q] = a0 * cv[q].x + a1 * cv[q].y + a2 * cv[q].z + a3 * cv[q].w;
+        acc[q][0] = fmaf(mq[q], a0, acc[q][0]);
+        acc[q][1] = fmaf(mq[q], a1, acc[q][1]);
+        acc[q][2] = fmaf(mq[q], a2, acc[q][2]);
+        acc[q][3] = fmaf(mq[q], a3, acc[q][3]);
       }
-      // gradient of the trilinear interpolant of sc with respect to y
-      const float gx = hM * (wy[0] * wz[0] * (sc[1] - sc[0]) + wy[1] * wz[0] * (sc[3] - sc[2]) +
-                             wy[0] * wz[1] * (sc[5] - sc[4]) + wy[1] * wz[1] * (sc[7] - sc[6]));
-      const float gyv = hM * (wx[0] * wz[0] * (sc[2] - sc[0]) + wx[1] * wz[0] * (sc[3] - sc[1]) +
-                              wx[0] * wz[1] * (sc[6] - sc[4]) + wx[1] * wz[1] * (sc[7] - sc[5]));
-      const float gz = hM * (wx[0] * wy[0] * (sc[4] - sc[0]) + wx[1] * wy[0] * (sc[5] - sc[1]) +
-                             wx[0] * wy[1] * (sc[6] - sc[2]) + wx[1] * wy[1] * (sc[7] - sc[3]));
+      // gradient with respect to y of the interpolant of the adjoint-weighted
+      // channels: al[q] = a . cf[q], d/dx of sum al[q] m_q, times dx/dy = hM
+      float al[8];
+#pragma unroll
+      for (int q = 1; q < 8; ++q) al[q] = a0 * cf[q][0] + a1 * cf[q][1] + a2 * cf[q][2] + a3 * cf[q][3];
+      const float gx = hM * (al[1] + al[3] * fy + al[5] * fz + al[7] * myz);
+      const float gyv = hM * (al[2] + al[3] * fx + al[6] * fz + al[7] * mxz);
+      const float gz = hM * (al[4] + al[5] * fx + al[6] * fy + al[7] * mxy);
       G0 += gx;
       G1 += gyv;
       G2 += gz;
@@ -702,6 +717,14 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
       if (j > jh) break;
       c = locate(A, B, (float)j * dt, M, hM);
     } while (c.idx == cell);
+    // monomial adjoint -> corner adjoint (transpose of the basis change)
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (!(q & bit))
+#pragma unroll
+          for (int ch = 0; ch < 4; ++ch) acc[q][ch] -= acc[q | bit][ch];
     // the next run's cell (if any) is c: when it is the neighbour across one
     // face, the 4 corners on that face carry over and only the other 4 flush
     const int dx = c.i[0] - ci0, dy = c.i[1] - ci1, dz = c.i[2] - ci2;
@@ -730,6 +753,14 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
       for (int q = 0; q < 8; ++q)
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) acc[q][ch] = nv[q][ch];
+      // back to the monomial basis (inverse of the corner transform above)
+#pragma unroll
+      for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (!(q & bit))
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) acc[q][ch] += acc[q | bit][ch];
     } else {
 #pragma unroll
       for (int q = 0; q < 8; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
