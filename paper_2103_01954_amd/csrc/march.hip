@@ -546,55 +546,33 @@ struct BwdOut {
 // banks (the [voxel][channel] order of device memory would put them on 8).
 __host__ __device__ __forceinline__ size_t lds_plane(int M) { return (size_t)M * M * M + 1; }
 
-// Add the register-accumulated gradients of the corners of one cell selected by
-// `corners` (bit q = corner q = dx + 2 dy + 4 dz): into the LDS copy of the
-// primitive's gradient (LDS_ACC, planar) or straight into device memory
-// ([voxel][channel]).  With the fade window the opacity gradient of a stored
-// voxel is the window times the gradient of its windowed value.  Into LDS, lane
-// L visits the corners in the order q ^ (L mod 8): lanes of one wave that
-// flush the same cell then add to different voxels in each instruction instead
-// of serialising on one address.
+// Add the register-accumulated gradients of one cell to the LDS copy of the
+// primitive's gradient (LDS_ACC, planar) or straight to device memory
+// ([voxel][channel]).  Register slot q holds corner q ^ m of the cell (corner
+// r = dx + 2 dy + 4 dz); `slots` selects the slots to add.  With the fade
+// window the opacity gradient of a stored voxel is the window times the
+// gradient of its windowed value.
 template <bool LDS_ACC, bool FADE>
 __device__ __forceinline__ void flush_cell(float *dst, size_t cell, int M, const float (&acc)[8][4],
-                                           const float (&wq)[8], unsigned corners) {
+                                           const float (&wq)[8], unsigned slots, unsigned m) {
   const size_t MM = (size_t)M * M;
-  float v[8][4];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    v[q][0] = acc[q][0];
-    v[q][1] = acc[q][1];
-    v[q][2] = acc[q][2];
-    v[q][3] = FADE ? acc[q][3] * wq[q] : acc[q][3];
-  }
-  const unsigned m = (LDS_ACC && kRotateFlush) ? (threadIdx.x & 7u) : 0u;
-  if (LDS_ACC && kRotateFlush) {   // v[q] <- v[q ^ m], one butterfly stage per bit of m
-#pragma unroll
-    for (int b = 1; b < 8; b <<= 1) {
-      const bool sw = (m & (unsigned)b) != 0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (q & b) continue;
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-          const float lo = v[q][ch], hi = v[q | b][ch];
-          v[q][ch] = sw ? hi : lo;
-          v[q | b][ch] = sw ? lo : hi;
-        }
-      }
-    }
-  }
   const size_t plane = lds_plane(M);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const unsigned r = (unsigned)q ^ m;        // the corner held in v[q]
-    if (!((corners >> r) & 1u)) continue;
+    if (!((slots >> q) & 1u)) continue;
+    const unsigned r = (unsigned)q ^ m;
     const size_t vox = cell + (r & 1u) + ((r >> 1) & 1u) * (size_t)M + (r >> 2) * MM;
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) {
-      if (LDS_ACC)
-        atomicAdd(dst + ch * plane + vox, v[q][ch]);
-      else
-        unsafeAtomicAdd(dst + vox * 4 + ch, v[q][ch]);
+    const float a3 = FADE ? acc[q][3] * wq[q] : acc[q][3];
+    if (LDS_ACC) {
+      atomicAdd(dst + vox, acc[q][0]);
+      atomicAdd(dst + plane + vox, acc[q][1]);
+      atomicAdd(dst + 2 * plane + vox, acc[q][2]);
+      atomicAdd(dst + 3 * plane + vox, a3);
+    } else {
+      unsafeAtomicAdd(dst + vox * 4, acc[q][0]);
+      unsafeAtomicAdd(dst + vox * 4 + 1, acc[q][1]);
+      unsafeAtomicAdd(dst + vox * 4 + 2, acc[q][2]);
+      unsafeAtomicAdd(dst + vox * 4 + 3, a3);
     }
   }
 }
@@ -633,6 +611,18 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
   float wq[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) wq[q] = 1.0f;
+  // Into LDS, lane L works in the cell coordinates mirrored along the axes
+  // named by the bits of m = L mod 8: its register slot q holds corner q ^ m,
+  // so lanes of one wave that flush the same cell add to different voxels in
+  // each instruction (instead of serialising on one address) at no cost in
+  // register moves.  Mirroring an axis maps its offset f to 1 - f and flips
+  // the sign of the derivative along it.
+  const unsigned m = (LDS_ACC && kRotateFlush) ? (threadIdx.x & 7u) : 0u;
+  const bool mx = m & 1u, my = (m >> 1) & 1u, mz = (m >> 2) & 1u;
+  const float hMx = mx ? -hM : hM, hMy = my ? -hM : hM, hMz = mz ? -hM : hM;
+  const int MMi = M * M;
+  const int so0 = (mx ? 1 : 0) + (my ? M : 0) + (mz ? MMi : 0);   // slot 0's voxel offset
+  const int sx = mx ? -1 : 1, sy = my ? -M : M, sz = mz ? -MMi : MMi;
   // One iteration per run of consecutive samples inside one voxel cell: the
   // corner loads before the run and the flush after it are executed by the
   // wave's lanes together (a per-sample "cell changed" branch would issue them
@@ -645,11 +635,21 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
   while (j <= jh) {
     const int cell = c.idx;
     const int ci0 = c.i[0], ci1 = c.i[1], ci2 = c.i[2];
-    load_corners<BF16>(pay, kb + cell, M, cv);
-    if (FADE) {
-      corner_fade(s_fade, c, wq);
+    {
+      const ptrdiff_t b0 = (ptrdiff_t)(kb + cell) + so0;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) cv[q].w *= wq[q];
+      for (int q = 0; q < 8; ++q)
+        cv[q] = Voxels<BF16>::load(pay, (size_t)(b0 + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0)));
+    }
+    if (FADE) {
+      const float wx[2] = {s_fade[ci0 + (mx ? 1 : 0)], s_fade[ci0 + (mx ? 0 : 1)]};
+      const float wy[2] = {s_fade[ci1 + (my ? 1 : 0)], s_fade[ci1 + (my ? 0 : 1)]};
+      const float wz[2] = {s_fade[ci2 + (mz ? 1 : 0)], s_fade[ci2 + (mz ? 0 : 1)]};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        wq[q] = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
+        cv[q].w *= wq[q];
+      }
     }
     // the cell's field in the monomial basis: f = sum_q cf[q] m_q with
     // m_q = product of the offsets (x, y, z) named by the bits of q
@@ -670,7 +670,9 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
           for (int ch = 0; ch < 4; ++ch) cf[q][ch] -= cf[q ^ bit][ch];
     do {
       const float tau = (float)j * dt;
-      const float fx = c.f[0], fy = c.f[1], fz = c.f[2];
+      const float fx = mx ? 1.0f - c.f[0] : c.f[0];
+      const float fy = my ? 1.0f - c.f[1] : c.f[1];
+      const float fz = mz ? 1.0f - c.f[2] : c.f[2];
       const float mxy = fx * fy, mxz = fx * fz, myz = fy * fz, mxyz = mxy * fz;
       const float mq[8] = {1.0f, fx, fy, mxy, fz, mxz, myz, mxyz};
       float val[4];
@@ -704,9 +706,9 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
       float al[8];
 #pragma unroll
       for (int q = 1; q < 8; ++q) al[q] = a0 * cf[q][0] + a1 * cf[q][1] + a2 * cf[q][2] + a3 * cf[q][3];
-      const float gx = hM * (al[1] + al[3] * fy + al[5] * fz + al[7] * myz);
-      const float gyv = hM * (al[2] + al[3] * fx + al[6] * fz + al[7] * mxz);
-      const float gz = hM * (al[4] + al[5] * fx + al[6] * fy + al[7] * mxy);
+      const float gx = hMx * (al[1] + al[3] * fy + al[5] * fz + al[7] * myz);
+      const float gyv = hMy * (al[2] + al[3] * fx + al[6] * fz + al[7] * mxz);
+      const float gz = hMz * (al[4] + al[5] * fx + al[6] * fy + al[7] * mxy);
       G0 += gx;
       G1 += gyv;
       G2 += gz;
@@ -730,14 +732,14 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
     const int dx = c.i[0] - ci0, dy = c.i[1] - ci1, dz = c.i[2] - ci2;
     const bool face = kShareFace && j <= jh && abs(dx) + abs(dy) + abs(dz) == 1;
     const int bit = dx ? 1 : (dy ? 2 : 4);
-    const bool up = dx + dy + dz > 0;
+    const bool up = (dx + dy + dz > 0) != ((m & (unsigned)bit) != 0);   // in the lane's mirrored axes
     // slot q is left behind (flushed) and refilled from slot q ^ bit iff
     // ((q & bit) != 0) == !up; the other slots move out and start at zero
     unsigned behind = 0;
 #pragma unroll
     for (int q = 0; q < 8; ++q)
       if (((q & bit) != 0) == !up) behind |= 1u << q;
-    if (gdst) flush_cell<LDS_ACC, FADE>(gdst, cell, M, acc, wq, face ? behind : 0xffu);
+    if (gdst) flush_cell<LDS_ACC, FADE>(gdst, cell, M, acc, wq, face ? behind : 0xffu, m);
     if (face && gdst) {
       float nv[8][4];
 #pragma unroll
