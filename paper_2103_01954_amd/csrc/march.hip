@@ -51,6 +51,14 @@ constexpr bool kChunkedPairs = true;
 // shared by consecutive cells in registers when a ray crosses one face.
 constexpr bool kRotateFlush = true;
 constexpr bool kShareFace = true;
+// The pairs of a work item are ordered by their number of samples (longest
+// first) and dealt round-robin, so the lanes of a wave replay pairs of about
+// the same length together; pairs without samples are dropped.
+#ifndef MVP_SORT_PAIRS
+#define MVP_SORT_PAIRS 1
+#endif
+constexpr bool kSortPairs = MVP_SORT_PAIRS;
+constexpr int kLenBuckets = 64;
 
 template <bool BF16>
 struct Voxels;
@@ -810,6 +818,16 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
 
 
 
+// Samples the backward replays for pair e: its samples up to the ray's last.
+__device__ __forceinline__ int pair_len(const AccelView &av, const mvp_ray_aux *__restrict__ aux, uint32_t e) {
+  const int2 jr = av.pj[e];
+  const int je = aux[__float_as_int(av.pb[e].w)].j_end;
+  return max(0, min(jr.y, je) - jr.x + 1);
+}
+
+// Length classes for ordering pairs: exact below 32 samples, then 4 wide.
+__device__ __forceinline__ int len_bucket(int n) { return n < 32 ? n : min(kLenBuckets - 1, 32 + ((n - 32) >> 2)); }
+
 // Backward, one workgroup per work item: up to kItemEntries culling-list
 // entries (tile, primitive k) of one primitive.  The pairs of those entries
 // (at most one per ray of each tile) are spread over the workgroup's threads;
@@ -827,8 +845,13 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
                                                              const void *__restrict__ pay,
                                                              const mvp_ray_aux *__restrict__ aux,
                                                              const float4 *__restrict__ grad_rgba,
-                                                             const RayConst *__restrict__ rc, BwdOut out) {
-  extern __shared__ float s_dyn[];      // [M^3*4] gradient (LDS_ACC), then [M] fade window (FADE)
+                                                             const RayConst *__restrict__ rc, BwdOut out,
+                                                             uint32_t sort_cap) {
+  extern __shared__ float s_dyn[];      // gradient (LDS_ACC), fade window (FADE), pair order and classes
+  __shared__ uint32_t s_live;
+  __shared__ uint32_t s_cls[kLenBuckets];
+  __shared__ uint32_t s_base[2][kLenBuckets];
+  __shared__ uint32_t s_wcnt[2][kTileThreads / kWave][kLenBuckets];
   __shared__ float s_pose[kTileThreads / kWave][16];
   __shared__ uint64_t s_start[kItemEntries];
   __shared__ uint32_t s_pre[kItemEntries + 1];
@@ -841,6 +864,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
   const bool pose = out.pos || out.rot || out.scale;
   float *s_grad = s_dyn;
   float *s_fade = s_dyn + ((LDS_ACC && out.pay) ? nlds : 0);
+  uint16_t *s_sort = (uint16_t *)(s_fade + (FADE ? M : 0));   // [sort_cap] pair order
+  uint8_t *s_pcls = (uint8_t *)(s_sort + sort_cap);              // [sort_cap] length class of pair i
   if (FADE) {
     fill_fade(s_fade, M, av.fade_alpha, av.fade_beta);
     __syncthreads();
@@ -884,6 +909,92 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
     float P[15];
 #pragma unroll
     for (int i = 0; i < 15; ++i) P[i] = 0.f;
+    if (kSortPairs && total <= sort_cap) {
+      // Counting sort of the item's pairs by length class, longest first, in a
+      // fixed order (class, then round r = the r-th pair of every thread's
+      // contiguous chunk, then wave, then lane), so the replay order, and with
+      // it every rounding, is the same from run to run; pairs of one class that
+      // are replayed together come from rays a chunk apart.  A histogram pass
+      // and a scan give the class bases; the scatter ranks each round by ballot
+      // within a wave and by per-wave counts across waves (double-buffered, one
+      // barrier per round).
+      const uint32_t per = (total + kTileThreads - 1) / kTileThreads;
+      const uint32_t c0 = threadIdx.x * per, c1 = min(total, c0 + per);
+      int q0 = 0;
+      if (c0 < c1) {
+        int hi = nent - 1;
+        while (q0 < hi) {
+          const int mid = (q0 + hi + 1) >> 1;
+          if (s_pre[mid] <= c0) q0 = mid; else hi = mid - 1;
+        }
+      }
+      if (threadIdx.x < kLenBuckets) s_cls[threadIdx.x] = 0;
+      __syncthreads();
+      for (uint32_t i = c0, q = q0; i < c1; ++i) {
+        while (s_pre[q + 1] <= i) ++q;
+        const int n = pair_len(av, aux, av.entry_pairs[s_start[q] + (i - s_pre[q])]);
+        const int b = n > 0 ? len_bucket(n) : 0xff;
+        s_pcls[i] = (uint8_t)b;
+        if (n > 0) atomicAdd(&s_cls[b], 1u);
+      }
+      __syncthreads();
+      if (wave == 0) {   // exclusive scan over the classes from the longest down
+        const uint32_t c = s_cls[kLenBuckets - 1 - lane];
+        uint32_t incl = c;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+          const uint32_t o = __shfl_up(incl, d, kWave);
+          if (lane >= d) incl += o;
+        }
+        s_base[0][kLenBuckets - 1 - lane] = incl - c;
+        if (lane == kWave - 1) s_live = incl;
+      }
+      const unsigned long long lt = (1ull << lane) - 1ull;
+      for (uint32_t r = 0; r < per; ++r) {
+        const int cur = r & 1;
+        const uint32_t i = c0 + r;
+        int b = -1;
+        if (i < c1) {
+          const int pb_ = s_pcls[i];
+          if (pb_ != 0xff) b = pb_;
+        }
+        s_wcnt[cur][wave][lane] = 0;   // kLenBuckets == kWave
+        uint32_t rank = 0;
+        unsigned long long todo = __ballot(b >= 0);
+        while (todo) {   // one class at a time: its lanes and their order
+          const int src = __ffsll((long long)todo) - 1;
+          const int bb = __shfl(b, src, kWave);
+          const unsigned long long mm = __ballot(b == bb);
+          if (b == bb) rank = (uint32_t)__popcll(mm & lt);
+          if (lane == src) s_wcnt[cur][wave][bb] = (uint32_t)__popcll(mm);
+          todo &= ~mm;
+        }
+        __syncthreads();
+        if (b >= 0) {
+          uint32_t pos = s_base[cur][b] + rank;
+          for (int w = 0; w < wave; ++w) pos += s_wcnt[cur][w][b];
+          s_sort[pos] = (uint16_t)i;
+        }
+        if (threadIdx.x < kLenBuckets) {
+          uint32_t add = 0;
+#pragma unroll
+          for (int w = 0; w < kTileThreads / kWave; ++w) add += s_wcnt[cur][w][threadIdx.x];
+          s_base[cur ^ 1][threadIdx.x] = s_base[cur][threadIdx.x] + add;
+        }
+      }
+      __syncthreads();
+      const uint32_t live = s_live;
+      for (uint32_t p = threadIdx.x; p < live; p += kTileThreads) {
+        const uint32_t i = s_sort[p];
+        int q = 0, hi = nent - 1;    // entry of flattened pair i: last q with s_pre[q] <= i
+        while (q < hi) {
+          const int mid = (q + hi + 1) >> 1;
+          if (s_pre[mid] <= i) q = mid; else hi = mid - 1;
+        }
+        const uint32_t e = av.entry_pairs[s_start[q] + (i - s_pre[q])];
+        bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, e, k, gdst, s_fade, pose, P);
+      }
+    } else {
     // kChunkedPairs: each thread replays a contiguous run of the flattened
     // pairs, so the lanes of a wave follow rays some pixels apart, which flush
     // into different voxel cells at once; otherwise pair i goes to thread
@@ -903,6 +1014,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
         const uint32_t e = av.entry_pairs[s_start[q] + (i - s_pre[q])];
         bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, e, k, gdst, s_fade, pose, P);
       }
+    }
     }
     if (pose) {
 #pragma unroll
@@ -943,6 +1055,11 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
 // floats): up to M = 16.
 constexpr size_t kLdsGradBytes = 64 * 1024 + 16;
 
+template <bool B, bool L, bool F>
+static const void *bwd_items_fn(bool w3) {
+  return w3 ? (const void *)k_bwd_items<B, L, F, 3> : (const void *)k_bwd_items<B, L, F, 1>;
+}
+
 hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_items_max,
                             const mvp_ray_aux *aux, const float *grad_rgba, const float *bg,
                             const float *rgba, RayConst *rc, float *g_pay, float *g_pos, float *g_rot,
@@ -966,32 +1083,46 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   if (e != hipSuccess || p.n_prim == 0 || n_items_max == 0) return e;
   const size_t lds = lds_plane(p.M) * 16;
   bool in_lds = lds <= kLdsGradBytes;
-  // 3 waves per SIMD when 3 workgroups' LDS fits a CU (160 KB; ~1 KB static)
-  const bool w3 = !(in_lds && g_pay) || 3 * (lds + fade_shm + 1024) <= 160 * 1024;
-  if (in_lds && g_pay) {
-    // allow more than the default dynamic LDS per workgroup (gfx950 has 160 KB)
-    const void *fn =
-        bf16 ? (fade ? (w3 ? (const void *)k_bwd_items<true, true, true, 3> : (const void *)k_bwd_items<true, true, true, 1>)
-                     : (w3 ? (const void *)k_bwd_items<true, true, false, 3> : (const void *)k_bwd_items<true, true, false, 1>))
-             : (fade ? (w3 ? (const void *)k_bwd_items<false, true, true, 3> : (const void *)k_bwd_items<false, true, true, 1>)
-                     : (w3 ? (const void *)k_bwd_items<false, true, false, 3> : (const void *)k_bwd_items<false, true, false, 1>));
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsGradBytes + 4096)) != hipSuccess) {
-      (void)hipGetLastError();
-      in_lds = lds + fade_shm <= 48 * 1024;
-    }
-  }
+  // 3 waves per SIMD when 3 workgroups' LDS fits a CU (160 KB; under 4 KB static)
+  const size_t kStatic = 4096;
+  const bool w3 = !(in_lds && g_pay) || 3 * (lds + fade_shm + kStatic) <= 160 * 1024;
   const unsigned grid = (unsigned)std::min<int64_t>(n_items_max, 1 << 20);
   BwdOut out{g_pay, g_pos, g_rot, g_scale};
-  const size_t shm = (in_lds && g_pay ? lds : 0) + fade_shm;
+  size_t shm = (in_lds && g_pay ? lds : 0) + fade_shm;
+  // the pair-ordering buffer takes what is left of the LDS share of a
+  // workgroup at the occupancy chosen above (items with more pairs than it
+  // holds keep their pairs in list order)
+  uint32_t sort_cap = 0;
+  if (kSortPairs) {
+    const size_t wgs = w3 ? 3 : (shm + kStatic <= 80 * 1024 ? 2 : 1);
+    const size_t share = 160 * 1024 / wgs - kStatic;
+    const size_t room = share > shm ? (share - shm) / (sizeof(uint16_t) + 1) : 0;
+    const size_t want = (size_t)av.item_entries * kTileThreads;
+    sort_cap = (uint32_t)(std::min(room, want) / kTileThreads * kTileThreads);
+    shm += (size_t)sort_cap * (sizeof(uint16_t) + 1);
+  }
+  if (shm > 64 * 1024) {
+    // allow more than the default dynamic LDS per workgroup (gfx950 has 160 KB)
+    const void *fn = bf16 ? (in_lds ? (fade ? bwd_items_fn<true, true, true>(w3) : bwd_items_fn<true, true, false>(w3))
+                                    : (fade ? bwd_items_fn<true, false, true>(w3) : bwd_items_fn<true, false, false>(w3)))
+                          : (in_lds ? (fade ? bwd_items_fn<false, true, true>(w3) : bwd_items_fn<false, true, false>(w3))
+                                    : (fade ? bwd_items_fn<false, false, true>(w3) : bwd_items_fn<false, false, false>(w3)));
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess) {
+      (void)hipGetLastError();
+      in_lds = false;   // gradients straight to device memory, pairs in list order
+      sort_cap = 0;
+      shm = fade_shm;
+    }
+  }
   if (t0) (void)hipEventRecord(t0, s);
 #define MVP_BWD(B, L, F)                                                                                      \
   do {                                                                                                        \
     if (w3)                                                                                                   \
       hipLaunchKernelGGL((k_bwd_items<B, L, F, 3>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale, \
-                         p.payload, aux, (const float4 *)grad_rgba, rc, out);                                 \
+                         p.payload, aux, (const float4 *)grad_rgba, rc, out, sort_cap);                       \
     else                                                                                                      \
       hipLaunchKernelGGL((k_bwd_items<B, L, F, 1>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale, \
-                         p.payload, aux, (const float4 *)grad_rgba, rc, out);                                 \
+                         p.payload, aux, (const float4 *)grad_rgba, rc, out, sort_cap);                       \
   } while (0)
   if (bf16) {
     if (in_lds) { if (fade) MVP_BWD(true, true, true); else MVP_BWD(true, true, false); }
