@@ -28,14 +28,17 @@
 // entries (screen tile, primitive) of one primitive: channel adjoints go to
 // the 8 voxel corners with the trilinear weights, accumulated in registers
 // over a run of samples in one cell and then in an LDS copy of the
-// primitive's gradient, which is added to device memory once per item; the
-// pose gradient (through y = A (o + t d - pos)) is reduced over the workgroup.
+// primitive's gradient (FP64 when it fits: LDS FP64 atomic adds run far
+// faster than FP32 ones on gfx950), which is added to device memory once per
+// item; the pose gradient (through y = A (o + t d - pos)) is reduced over the
+// workgroup.
 //
 // Built with -ffp-contract=off; fused multiply-adds are written explicitly.
 #include <hip/hip_runtime.h>
 #include <stdlib.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <climits>
 
 #include "internal.h"
@@ -59,6 +62,11 @@ constexpr bool kShareFace = true;
 #endif
 constexpr bool kSortPairs = MVP_SORT_PAIRS;
 constexpr int kLenBuckets = 64;
+// The LDS copy of a primitive's payload gradient may be held in FP64.
+#ifndef MVP_WIDE_GRAD
+#define MVP_WIDE_GRAD 1
+#endif
+constexpr bool kWideGrad = MVP_WIDE_GRAD;
 
 template <bool BF16>
 struct Voxels;
@@ -560,8 +568,8 @@ __host__ __device__ __forceinline__ size_t lds_plane(int M) { return (size_t)M *
 // r = dx + 2 dy + 4 dz); `slots` selects the slots to add.  With the fade
 // window the opacity gradient of a stored voxel is the window times the
 // gradient of its windowed value.
-template <bool LDS_ACC, bool FADE>
-__device__ __forceinline__ void flush_cell(float *dst, size_t cell, int M, const float (&acc)[8][4],
+template <bool LDS_ACC, bool FADE, typename T>
+__device__ __forceinline__ void flush_cell(T *dst, size_t cell, int M, const float (&acc)[8][4],
                                            const float (&wq)[8], unsigned slots, unsigned m) {
   const size_t MM = (size_t)M * M;
   const size_t plane = lds_plane(M);
@@ -571,11 +579,11 @@ __device__ __forceinline__ void flush_cell(float *dst, size_t cell, int M, const
     const unsigned r = (unsigned)q ^ m;
     const size_t vox = cell + (r & 1u) + ((r >> 1) & 1u) * (size_t)M + (r >> 2) * MM;
     const float a3 = FADE ? acc[q][3] * wq[q] : acc[q][3];
-    if (LDS_ACC) {
-      atomicAdd(dst + vox, acc[q][0]);
-      atomicAdd(dst + plane + vox, acc[q][1]);
-      atomicAdd(dst + 2 * plane + vox, acc[q][2]);
-      atomicAdd(dst + 3 * plane + vox, a3);
+    if constexpr (LDS_ACC) {
+      atomicAdd(dst + vox, (T)acc[q][0]);
+      atomicAdd(dst + plane + vox, (T)acc[q][1]);
+      atomicAdd(dst + 2 * plane + vox, (T)acc[q][2]);
+      atomicAdd(dst + 3 * plane + vox, (T)a3);
     } else {
       unsafeAtomicAdd(dst + vox * 4, acc[q][0]);
       unsafeAtomicAdd(dst + vox * 4 + 1, acc[q][1]);
@@ -589,11 +597,11 @@ __device__ __forceinline__ void flush_cell(float *dst, size_t cell, int M, const
 // voxel corners (registers while the samples stay in one cell, then gdst:
 // the LDS copy of k's gradient or device memory) and the pose chain of the
 // pair added to P (dL/dt 3, dL/dR 9 row-major, dL/ds 3).
-template <bool BF16, bool LDS_ACC, bool FADE>
+template <bool BF16, bool LDS_ACC, bool FADE, typename GAcc>
 __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__restrict__ rot,
                                          const float *__restrict__ scale, const void *__restrict__ pay,
                                          const mvp_ray_aux *__restrict__ aux, const float4 *__restrict__ grad_rgba,
-                                         const RayConst *__restrict__ rc, uint32_t e, int k, float *gdst,
+                                         const RayConst *__restrict__ rc, uint32_t e, int k, GAcc *gdst,
                                          const float *s_fade, bool pose, float (&P)[15]) {
   const int M = av.M;
   const float hM = 0.5f * (float)(M - 1);
@@ -831,14 +839,14 @@ __device__ __forceinline__ int len_bucket(int n) { return n < 32 ? n : min(kLenB
 // Backward, one workgroup per work item: up to kItemEntries culling-list
 // entries (tile, primitive k) of one primitive.  The pairs of those entries
 // (at most one per ray of each tile) are spread over the workgroup's threads;
-// the payload gradient of k is accumulated in LDS (LDS_ACC) and added to
-// device memory once per item, the pose gradient is reduced over the
-// workgroup and added with 15 atomics.
+// the payload gradient of k is accumulated in LDS (LDS_ACC; in FP64 when
+// WIDE) and added to device memory once per item, the pose gradient is
+// reduced over the workgroup and added with 15 atomics.
 //
 // WAVES > 1 asks the compiler for that many waves per SIMD (it then keeps the
 // kernel within 512 / WAVES registers, spilling a few); it is used when the
 // LDS gradient leaves room for that many workgroups per CU.
-template <bool BF16, bool LDS_ACC, bool FADE, int WAVES>
+template <bool BF16, bool LDS_ACC, bool FADE, int WAVES, bool WIDE>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_bwd_items(
     AccelView av, const float *__restrict__ rot,
                                                              const float *__restrict__ scale,
@@ -847,7 +855,9 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
                                                              const float4 *__restrict__ grad_rgba,
                                                              const RayConst *__restrict__ rc, BwdOut out,
                                                              uint32_t sort_cap) {
-  extern __shared__ float s_dyn[];      // gradient (LDS_ACC), fade window (FADE), pair order and classes
+  // gradient (LDS_ACC; FP64 when WIDE), fade window (FADE), pair order and classes
+  extern __shared__ double s_dyn[];
+  using GAcc = typename std::conditional<LDS_ACC && WIDE, double, float>::type;
   __shared__ uint32_t s_live;
   __shared__ uint32_t s_cls[kLenBuckets];
   __shared__ uint32_t s_base[2][kLenBuckets];
@@ -862,8 +872,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
   const int nlds = (int)(lds_plane(M) * 4);       // their planar LDS copy
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const bool pose = out.pos || out.rot || out.scale;
-  float *s_grad = s_dyn;
-  float *s_fade = s_dyn + ((LDS_ACC && out.pay) ? nlds : 0);
+  GAcc *s_grad = (GAcc *)s_dyn;
+  float *s_fade = (float *)((char *)s_dyn + ((LDS_ACC && out.pay) ? (size_t)nlds * sizeof(GAcc) : 0));
   uint16_t *s_sort = (uint16_t *)(s_fade + (FADE ? M : 0));   // [sort_cap] pair order
   uint8_t *s_pcls = (uint8_t *)(s_sort + sort_cap);              // [sort_cap] length class of pair i
   if (FADE) {
@@ -902,10 +912,15 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
       if (lane < kItemEntries) s_pre[lane + 1] = incl;
     }
     if (LDS_ACC && out.pay)
-      for (int i = threadIdx.x; i < nlds; i += kTileThreads) s_grad[i] = 0.f;
+      for (int i = threadIdx.x; i < nlds; i += kTileThreads) s_grad[i] = (GAcc)0;
     __syncthreads();
     const uint32_t total = s_pre[nent];
-    float *gdst = out.pay ? (LDS_ACC ? s_grad : out.pay + (size_t)k * M3 * 4) : nullptr;
+    GAcc *gdst = nullptr;
+    if constexpr (LDS_ACC) {
+      if (out.pay) gdst = s_grad;
+    } else {
+      if (out.pay) gdst = out.pay + (size_t)k * M3 * 4;
+    }
     float P[15];
 #pragma unroll
     for (int i = 0; i < 15; ++i) P[i] = 0.f;
@@ -1043,7 +1058,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
       float *dst = out.pay + M3 * 4 * (size_t)k;
       const size_t plane = lds_plane(M);
       for (int i = threadIdx.x; i < nacc; i += kTileThreads) {   // device order: voxel i/4, channel i%4
-        const float x = s_grad[(i & 3) * plane + (i >> 2)];
+        const float x = (float)s_grad[(i & 3) * plane + (i >> 2)];
         if (x != 0.f) unsafeAtomicAdd(dst + i, x);
       }
     }
@@ -1055,9 +1070,9 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
 // floats): up to M = 16.
 constexpr size_t kLdsGradBytes = 64 * 1024 + 16;
 
-template <bool B, bool L, bool F>
+template <bool B, bool L, bool F, bool W>
 static const void *bwd_items_fn(bool w3) {
-  return w3 ? (const void *)k_bwd_items<B, L, F, 3> : (const void *)k_bwd_items<B, L, F, 1>;
+  return w3 ? (const void *)k_bwd_items<B, L, F, 3, W> : (const void *)k_bwd_items<B, L, F, 1, W>;
 }
 
 hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_items_max,
@@ -1081,11 +1096,21 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
 #undef MVP_RAYS
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || p.n_prim == 0 || n_items_max == 0) return e;
-  const size_t lds = lds_plane(p.M) * 16;
-  bool in_lds = lds <= kLdsGradBytes;
-  // 3 waves per SIMD when 3 workgroups' LDS fits a CU (160 KB; under 4 KB static)
-  const size_t kStatic = 4096;
-  const bool w3 = !(in_lds && g_pay) || 3 * (lds + fade_shm + kStatic) <= 160 * 1024;
+  const size_t lds32 = lds_plane(p.M) * 4 * sizeof(float), lds64 = lds_plane(p.M) * 4 * sizeof(double);
+  bool in_lds = lds32 <= kLdsGradBytes;
+  const size_t kStatic = 4096;   // the kernel's static LDS is under 4 KB
+  auto wgs_per_cu = [&](size_t grad) {
+    for (int w = 3; w > 1; --w)
+      if ((size_t)w * (grad + fade_shm + kStatic) <= 160 * 1024) return w;
+    return 1;
+  };
+  // The LDS gradient is held in FP64 whenever it fits: on gfx950 an LDS FP64
+  // atomic add sustains about 20 times the lane rate of an FP32 one, which
+  // outweighs the fewer workgroups per CU (16^3: one instead of two).
+  bool wide = kWideGrad && in_lds && g_pay && lds64 + fade_shm + kStatic <= 160 * 1024;
+  const size_t lds = wide ? lds64 : lds32;
+  // 3 waves per SIMD when 3 workgroups' LDS fits a CU
+  const bool w3 = !(in_lds && g_pay) || wgs_per_cu(lds) >= 3;
   const unsigned grid = (unsigned)std::min<int64_t>(n_items_max, 1 << 20);
   BwdOut out{g_pay, g_pos, g_rot, g_scale};
   size_t shm = (in_lds && g_pay ? lds : 0) + fade_shm;
@@ -1103,34 +1128,43 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   }
   if (shm > 64 * 1024) {
     // allow more than the default dynamic LDS per workgroup (gfx950 has 160 KB)
-    const void *fn = bf16 ? (in_lds ? (fade ? bwd_items_fn<true, true, true>(w3) : bwd_items_fn<true, true, false>(w3))
-                                    : (fade ? bwd_items_fn<true, false, true>(w3) : bwd_items_fn<true, false, false>(w3)))
-                          : (in_lds ? (fade ? bwd_items_fn<false, true, true>(w3) : bwd_items_fn<false, true, false>(w3))
-                                    : (fade ? bwd_items_fn<false, false, true>(w3) : bwd_items_fn<false, false, false>(w3)));
+    const void *fn =
+        bf16 ? (in_lds ? (wide ? (fade ? bwd_items_fn<true, true, true, true>(w3) : bwd_items_fn<true, true, false, true>(w3))
+                               : (fade ? bwd_items_fn<true, true, true, false>(w3) : bwd_items_fn<true, true, false, false>(w3)))
+                       : (fade ? bwd_items_fn<true, false, true, false>(w3) : bwd_items_fn<true, false, false, false>(w3)))
+             : (in_lds ? (wide ? (fade ? bwd_items_fn<false, true, true, true>(w3) : bwd_items_fn<false, true, false, true>(w3))
+                               : (fade ? bwd_items_fn<false, true, true, false>(w3) : bwd_items_fn<false, true, false, false>(w3)))
+                       : (fade ? bwd_items_fn<false, false, true, false>(w3) : bwd_items_fn<false, false, false, false>(w3)));
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess) {
       (void)hipGetLastError();
       in_lds = false;   // gradients straight to device memory, pairs in list order
+      wide = false;
       sort_cap = 0;
       shm = fade_shm;
     }
   }
   if (t0) (void)hipEventRecord(t0, s);
-#define MVP_BWD(B, L, F)                                                                                      \
+#define MVP_BWD(B, L, F, W)                                                                                   \
   do {                                                                                                        \
     if (w3)                                                                                                   \
-      hipLaunchKernelGGL((k_bwd_items<B, L, F, 3>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale, \
-                         p.payload, aux, (const float4 *)grad_rgba, rc, out, sort_cap);                       \
+      hipLaunchKernelGGL((k_bwd_items<B, L, F, 3, W>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot,        \
+                         p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, out, sort_cap);              \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_bwd_items<B, L, F, 1>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale, \
-                         p.payload, aux, (const float4 *)grad_rgba, rc, out, sort_cap);                       \
+      hipLaunchKernelGGL((k_bwd_items<B, L, F, 1, W>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot,        \
+                         p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, out, sort_cap);              \
+  } while (0)
+#define MVP_BWD_F(B, F)                                                                                       \
+  do {                                                                                                        \
+    if (in_lds && wide) MVP_BWD(B, true, F, true);                                                            \
+    else if (in_lds) MVP_BWD(B, true, F, false);                                                              \
+    else MVP_BWD(B, false, F, false);                                                                         \
   } while (0)
   if (bf16) {
-    if (in_lds) { if (fade) MVP_BWD(true, true, true); else MVP_BWD(true, true, false); }
-    else { if (fade) MVP_BWD(true, false, true); else MVP_BWD(true, false, false); }
+    if (fade) MVP_BWD_F(true, true); else MVP_BWD_F(true, false);
   } else {
-    if (in_lds) { if (fade) MVP_BWD(false, true, true); else MVP_BWD(false, true, false); }
-    else { if (fade) MVP_BWD(false, false, true); else MVP_BWD(false, false, false); }
+    if (fade) MVP_BWD_F(false, true); else MVP_BWD_F(false, false);
   }
+#undef MVP_BWD_F
 #undef MVP_BWD
   e = hipGetLastError();
   if (t1) (void)hipEventRecord(t1, s);
