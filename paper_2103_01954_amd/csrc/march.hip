@@ -50,10 +50,8 @@ namespace mvp {
 // item's pairs are dealt to its threads.
 constexpr int kItemEntries = 64;
 constexpr bool kChunkedPairs = true;
-// Gradient flushes rotate the corner order per lane, and keep the 4 corners
-// shared by consecutive cells in registers when a ray crosses one face.
+// Gradient flushes rotate the corner order per lane.
 constexpr bool kRotateFlush = true;
-constexpr bool kShareFace = true;
 // The pairs of a work item are ordered by their number of samples (longest
 // first) and dealt round-robin, so the lanes of a wave replay pairs of about
 // the same length together; pairs without samples are dropped.
@@ -743,46 +741,9 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
         if (!(q & bit))
 #pragma unroll
           for (int ch = 0; ch < 4; ++ch) acc[q][ch] -= acc[q | bit][ch];
-    // the next run's cell (if any) is c: when it is the neighbour across one
-    // face, the 4 corners on that face carry over and only the other 4 flush
-    const int dx = c.i[0] - ci0, dy = c.i[1] - ci1, dz = c.i[2] - ci2;
-    const bool face = kShareFace && j <= jh && abs(dx) + abs(dy) + abs(dz) == 1;
-    const int bit = dx ? 1 : (dy ? 2 : 4);
-    const bool up = (dx + dy + dz > 0) != ((m & (unsigned)bit) != 0);   // in the lane's mirrored axes
-    // slot q is left behind (flushed) and refilled from slot q ^ bit iff
-    // ((q & bit) != 0) == !up; the other slots move out and start at zero
-    unsigned behind = 0;
+    if (gdst) flush_cell<LDS_ACC, FADE>(gdst, cell, M, acc, wq, 0xffu, m);
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (((q & bit) != 0) == !up) behind |= 1u << q;
-    if (gdst) flush_cell<LDS_ACC, FADE>(gdst, cell, M, acc, wq, face ? behind : 0xffu, m);
-    if (face && gdst) {
-      float nv[8][4];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const bool refill = (behind >> q) & 1u;
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-          const float partner = bit == 1 ? acc[q ^ 1][ch] : (bit == 2 ? acc[q ^ 2][ch] : acc[q ^ 4][ch]);
-          nv[q][ch] = refill ? partner : 0.f;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) acc[q][ch] = nv[q][ch];
-      // back to the monomial basis (inverse of the corner transform above)
-#pragma unroll
-      for (int bit = 1; bit < 8; bit <<= 1)
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (!(q & bit))
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) acc[q][ch] += acc[q | bit][ch];
-    } else {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
-    }
+    for (int q = 0; q < 8; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
   }
   if (!pose) return;
   // y = A (o + tau d - t), A = diag(1/s) R^T; d is the unit pixel ray
