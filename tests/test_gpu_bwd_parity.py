@@ -155,8 +155,8 @@ def test_autograd_function_matches_direct_backward(mvp_ctx):
 
 @pytest.mark.parametrize("m", [16, 20], ids=["M16-lds", "M20-global"])
 def test_large_grid_gradients(mvp_ctx, m):
-    """M=16 accumulates a primitive's gradient in 64 KiB of LDS; M=20 exceeds it
-    and accumulates in device memory."""
+    """M=16 accumulates a primitive's gradient in a 128 KiB FP64 copy in LDS;
+    M=20 does not fit and accumulates straight into device memory."""
     prims = scenes.random_box_scene(91, n=5, m=m, s_lo=0.3, s_hi=0.6)
     cam = scenes.look_at_camera(np.random.default_rng(92), 40, 40)
     params = scenes.MarchParams(1 / 256, 1e-4)
