@@ -206,7 +206,11 @@ def main():
             "traffic_gbs": round(traffic / (kms / 1e3) / 1e9, 1) if traffic else None, "kernel": kern,
             "kernel_ms": round(kms, 3), "bytes_per_prim_sample": per,
             "kernel_ms_each": {KERN_FWD: round(fwd_ms, 3), KERN_BWD: round(bwd_ms, 3)},
-            "call_ms": {"render_fwd": round(fwd_call_ms, 3), "render_bwd": round(bwd_call_ms, 3)}}
+            "call_ms": {"render_fwd": round(fwd_call_ms, 3), "render_bwd": round(bwd_call_ms, 3)},
+            # the whole step (build + forward + backward) against the gather roofline of the
+            # forward's and backward's bytes together: prim-samples/s x bytes / HBM peak
+            "step_gather_frac": round(prim_s / (ms / 1e3) * (BYTES_FWD[dtype] + BYTES_BWD[dtype]) /
+                                      (HBM_PEAK_GBS * 1e9), 4)}
 
     # a plain device copy: the calibration dispatch for the HBM byte counters
     # (--copy-calib-mib), and the measured copy bandwidth of this GPU
