@@ -85,12 +85,6 @@ struct Voxels<true> {
   }
 };
 
-__device__ __forceinline__ float lerpf(float a, float b, float f) { return fmaf(f, b - a, a); }
-
-__device__ __forceinline__ float4 lerp4(float4 a, float4 b, float f) {
-  return make_float4(lerpf(a.x, b.x, f), lerpf(a.y, b.y, f), lerpf(a.z, b.z, f), lerpf(a.w, b.w, f));
-}
-
 // Position of sample tau in a primitive's voxel grid (align-corners): index of
 // the lower corner of the cell and the fractional offsets.
 struct Cell {
@@ -115,27 +109,6 @@ __device__ __forceinline__ Cell locate(const float4 &A, const float4 &B, float t
   }
   c.idx = (i0[2] * M + i0[1]) * M + i0[0];
   return c;
-}
-
-// Trilinear RGBA at a cell (lerp along x, then y, then z).
-template <bool BF16>
-__device__ __forceinline__ float4 trilinear(const void *pay, size_t base, int M, const Cell &c) {
-  const size_t MM = (size_t)M * M;
-  const float4 v000 = Voxels<BF16>::load(pay, base);
-  const float4 v100 = Voxels<BF16>::load(pay, base + 1);
-  const float4 v010 = Voxels<BF16>::load(pay, base + M);
-  const float4 v110 = Voxels<BF16>::load(pay, base + M + 1);
-  const float4 v001 = Voxels<BF16>::load(pay, base + MM);
-  const float4 v101 = Voxels<BF16>::load(pay, base + MM + 1);
-  const float4 v011 = Voxels<BF16>::load(pay, base + MM + M);
-  const float4 v111 = Voxels<BF16>::load(pay, base + MM + M + 1);
-  const float4 c00 = lerp4(v000, v100, c.f[0]);
-  const float4 c10 = lerp4(v010, v110, c.f[0]);
-  const float4 c01 = lerp4(v001, v101, c.f[0]);
-  const float4 c11 = lerp4(v011, v111, c.f[0]);
-  const float4 c0 = lerp4(c00, c10, c.f[1]);
-  const float4 c1 = lerp4(c01, c11, c.f[1]);
-  return lerp4(c0, c1, c.f[2]);
 }
 
 __device__ __forceinline__ int jlo_of(const float4 &A) { return __float_as_int(A.w); }
@@ -172,15 +145,22 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // forward
 // ---------------------------------------------------------------------------
 
-// Trilinear RGBA from the 8 cached corners of a cell (corner q = dx + 2 dy + 4 dz).
+// Trilinear RGBA from the 8 cached corners of a cell (corner q = dx + 2 dy + 4 dz):
+// the 8 corner weights once, then one weighted sum per channel.
 __device__ __forceinline__ float4 trilerp(const float4 (&v)[8], const Cell &c) {
-  const float4 c00 = lerp4(v[0], v[1], c.f[0]);
-  const float4 c10 = lerp4(v[2], v[3], c.f[0]);
-  const float4 c01 = lerp4(v[4], v[5], c.f[0]);
-  const float4 c11 = lerp4(v[6], v[7], c.f[0]);
-  const float4 c0 = lerp4(c00, c10, c.f[1]);
-  const float4 c1 = lerp4(c01, c11, c.f[1]);
-  return lerp4(c0, c1, c.f[2]);
+  const float fx = c.f[0], fy = c.f[1], fz = c.f[2];
+  const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+  const float yz[4] = {gy * gz, fy * gz, gy * fz, fy * fz};
+  float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const float w = ((q & 1) ? fx : gx) * yz[q >> 1];
+    r.x = fmaf(w, v[q].x, r.x);
+    r.y = fmaf(w, v[q].y, r.y);
+    r.z = fmaf(w, v[q].z, r.z);
+    r.w = fmaf(w, v[q].w, r.w);
+  }
+  return r;
 }
 
 template <bool BF16>
@@ -400,7 +380,7 @@ __device__ void march_ray(const AccelView &av, const void *pay, const float *fad
 }
 
 template <bool BF16, bool FADE>
-__global__ __launch_bounds__(kTileThreads) void k_march_fwd(AccelView av, const void *__restrict__ pay,
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_march_fwd(AccelView av, const void *__restrict__ pay,
                                                              const float *__restrict__ bg,
                                                              float4 *__restrict__ rgba,
                                                              mvp_ray_aux *__restrict__ aux,
