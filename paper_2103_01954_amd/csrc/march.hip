@@ -95,19 +95,19 @@ struct Cell {
 
 __device__ __forceinline__ Cell locate(const float4 &A, const float4 &B, float tau, int M, float hM) {
   const float y[3] = {fmaf(tau, B.x, A.x), fmaf(tau, B.y, A.y), fmaf(tau, B.z, A.z)};
-  int i0[3];
+  const float top = (float)(M - 2);
   Cell c;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
+    // u is in [0, M-1] (fma(-1, hM, hM) is exactly 0), so the lower corner is
+    // floor(u), except u = M-1, which belongs to the last cell with offset 1
     const float yc = fminf(fmaxf(y[i], -1.0f), 1.0f);
     const float u = fmaf(yc, hM, hM);
-    int q = (int)floorf(u);
-    q = min(max(q, 0), M - 2);
-    i0[i] = q;
-    c.i[i] = q;
-    c.f[i] = u - (float)q;
+    const float qf = fminf(floorf(u), top);
+    c.i[i] = (int)qf;
+    c.f[i] = u - qf;
   }
-  c.idx = (i0[2] * M + i0[1]) * M + i0[0];
+  c.idx = (c.i[2] * M + c.i[1]) * M + c.i[0];
   return c;
 }
 
