@@ -46,11 +46,13 @@
 namespace mvp {
 
 // Largest number of culling-list entries per backward work item (the build
-// picks the number per structure, see backward_item_entries), and how a work
-// item's pairs are dealt to its threads.
+// picks the number per structure, see backward_item_entries), and how the
+// pairs of an item too large for the ordering buffer (below) are dealt to its
+// threads.
 constexpr int kItemEntries = 64;
 constexpr bool kChunkedPairs = true;
-// Gradient flushes rotate the corner order per lane.
+// Lanes accumulate in cell coordinates mirrored by (lane mod 8), so lanes that
+// flush the same cell add to different corners in each instruction.
 constexpr bool kRotateFlush = true;
 // The pairs of a work item are ordered by their number of samples (longest
 // first) and dealt round-robin, so the lanes of a wave replay pairs of about
@@ -951,6 +953,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
         bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, e, k, gdst, s_fade, pose, P);
       }
     } else {
+    // list order (more pairs than the ordering buffer holds).
     // kChunkedPairs: each thread replays a contiguous run of the flattened
     // pairs, so the lanes of a wave follow rays some pixels apart, which flush
     // into different voxel cells at once; otherwise pair i goes to thread
