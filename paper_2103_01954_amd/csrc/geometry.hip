@@ -654,7 +654,7 @@ hipError_t launch_hit_count(const AccelView &av, int mode, uint32_t *ray_cnt, ui
 // each output line is completed in one burst instead of piece by piece.  Mode
 // 1 writes only the primitive ids of the slab hits into `ids`, in primitive-id
 // order.
-constexpr int kKeys = 16;
+constexpr int kKeys = 24;
 
 __global__ __launch_bounds__(kTileThreads) void k_hit_emit(AccelView av, int mode, int32_t *__restrict__ tkey,
                                                             uint32_t *__restrict__ trank, float4 *__restrict__ pa,

@@ -11,7 +11,7 @@ namespace mvp {
 constexpr int kTile = 16;                  // screen tile edge in pixels
 constexpr int kTileThreads = kTile * kTile;  // one thread per pixel of a tile
 constexpr int kWave = 64;                  // CDNA wavefront width
-constexpr int kStage = 256;                // culling-list entries staged in LDS per pass
+constexpr int kStage = 128;                // culling-list entries staged in LDS per pass
 constexpr int kJMax = (1 << 24) - 1;       // largest sample index with an exact float value
 
 // Camera as the kernels see it: origin, pixel->direction matrix and its inverse
