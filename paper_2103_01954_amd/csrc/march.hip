@@ -67,6 +67,11 @@ constexpr int kLenBuckets = 64;
 #define MVP_WIDE_GRAD 1
 #endif
 constexpr bool kWideGrad = MVP_WIDE_GRAD;
+// 512-thread backward workgroups when the LDS gradient leaves room for one.
+#ifndef MVP_WIDE_WG
+#define MVP_WIDE_WG 1
+#endif
+constexpr bool kWideWorkgroup = MVP_WIDE_WG;
 
 template <bool BF16>
 struct Voxels;
@@ -788,9 +793,11 @@ __device__ __forceinline__ int len_bucket(int n) { return n < 32 ? n : min(kLenB
 //
 // WAVES > 1 asks the compiler for that many waves per SIMD (it then keeps the
 // kernel within 512 / WAVES registers, spilling a few); it is used when the
-// LDS gradient leaves room for that many workgroups per CU.
-template <bool BF16, bool LDS_ACC, bool FADE, int WAVES, bool WIDE>
-__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_bwd_items(
+// LDS gradient leaves room for that many workgroups per CU.  THREADS is the
+// workgroup size: 512 when the LDS gradient leaves room for one workgroup per
+// CU, so that the CU still runs two waves per SIMD.
+template <bool BF16, bool LDS_ACC, bool FADE, int WAVES, bool WIDE, int THREADS>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_bwd_items(
     AccelView av, const float *__restrict__ rot,
                                                              const float *__restrict__ scale,
                                                              const void *__restrict__ pay,
@@ -804,8 +811,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
   __shared__ uint32_t s_live;
   __shared__ uint32_t s_cls[kLenBuckets];
   __shared__ uint32_t s_base[2][kLenBuckets];
-  __shared__ uint32_t s_wcnt[2][kTileThreads / kWave][kLenBuckets];
-  __shared__ float s_pose[kTileThreads / kWave][16];
+  __shared__ uint32_t s_wcnt[2][THREADS / kWave][kLenBuckets];
+  __shared__ float s_pose[THREADS / kWave][16];
   __shared__ uint64_t s_start[kItemEntries];
   __shared__ uint32_t s_pre[kItemEntries + 1];
   __shared__ int s_prim;
@@ -855,7 +862,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
       if (lane < kItemEntries) s_pre[lane + 1] = incl;
     }
     if (LDS_ACC && out.pay)
-      for (int i = threadIdx.x; i < nlds; i += kTileThreads) s_grad[i] = (GAcc)0;
+      for (int i = threadIdx.x; i < nlds; i += THREADS) s_grad[i] = (GAcc)0;
     __syncthreads();
     const uint32_t total = s_pre[nent];
     GAcc *gdst = nullptr;
@@ -876,7 +883,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
       // and a scan give the class bases; the scatter ranks each round by ballot
       // within a wave and by per-wave counts across waves (double-buffered, one
       // barrier per round).
-      const uint32_t per = (total + kTileThreads - 1) / kTileThreads;
+      const uint32_t per = (total + THREADS - 1) / THREADS;
       const uint32_t c0 = threadIdx.x * per, c1 = min(total, c0 + per);
       int q0 = 0;
       if (c0 < c1) {
@@ -936,13 +943,13 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
         if (threadIdx.x < kLenBuckets) {
           uint32_t add = 0;
 #pragma unroll
-          for (int w = 0; w < kTileThreads / kWave; ++w) add += s_wcnt[cur][w][threadIdx.x];
+          for (int w = 0; w < THREADS / kWave; ++w) add += s_wcnt[cur][w][threadIdx.x];
           s_base[cur ^ 1][threadIdx.x] = s_base[cur][threadIdx.x] + add;
         }
       }
       __syncthreads();
       const uint32_t live = s_live;
-      for (uint32_t p = threadIdx.x; p < live; p += kTileThreads) {
+      for (uint32_t p = threadIdx.x; p < live; p += THREADS) {
         const uint32_t i = s_sort[p];
         int q = 0, hi = nent - 1;    // entry of flattened pair i: last q with s_pre[q] <= i
         while (q < hi) {
@@ -958,8 +965,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
     // pairs, so the lanes of a wave follow rays some pixels apart, which flush
     // into different voxel cells at once; otherwise pair i goes to thread
     // i mod 256 (neighbouring pixels on neighbouring lanes).
-    const uint32_t per = kChunkedPairs ? (total + kTileThreads - 1) / kTileThreads : 1;
-    const uint32_t stride = kChunkedPairs ? 1 : kTileThreads;
+    const uint32_t per = kChunkedPairs ? (total + THREADS - 1) / THREADS : 1;
+    const uint32_t stride = kChunkedPairs ? 1 : THREADS;
     uint32_t i = kChunkedPairs ? threadIdx.x * per : threadIdx.x;
     const uint32_t iend = kChunkedPairs ? min(total, i + per) : total;
     if (i < iend) {
@@ -988,7 +995,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
     if (pose && threadIdx.x < 15 && total > 0) {
       float x = 0.f;
 #pragma unroll
-      for (int w = 0; w < kTileThreads / kWave; ++w) x += s_pose[w][threadIdx.x];
+      for (int w = 0; w < THREADS / kWave; ++w) x += s_pose[w][threadIdx.x];
       const int i = threadIdx.x;
       if (i < 3) {
         if (out.pos) unsafeAtomicAdd(out.pos + 3 * (size_t)k + i, x);
@@ -1001,7 +1008,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
     if (LDS_ACC && out.pay && total > 0) {
       float *dst = out.pay + M3 * 4 * (size_t)k;
       const size_t plane = lds_plane(M);
-      for (int i = threadIdx.x; i < nacc; i += kTileThreads) {   // device order: voxel i/4, channel i%4
+      for (int i = threadIdx.x; i < nacc; i += THREADS) {   // device order: voxel i/4, channel i%4
         const float x = (float)s_grad[(i & 3) * plane + (i >> 2)];
         if (x != 0.f) unsafeAtomicAdd(dst + i, x);
       }
@@ -1015,8 +1022,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
 constexpr size_t kLdsGradBytes = 64 * 1024 + 16;
 
 template <bool B, bool L, bool F, bool W>
-static const void *bwd_items_fn(bool w3) {
-  return w3 ? (const void *)k_bwd_items<B, L, F, 3, W> : (const void *)k_bwd_items<B, L, F, 1, W>;
+static const void *bwd_items_fn(bool w3, bool wide_wg) {
+  return w3 ? (const void *)k_bwd_items<B, L, F, 3, W, kTileThreads>
+            : (wide_wg ? (const void *)k_bwd_items<B, L, F, 1, W, 2 * kTileThreads>
+                       : (const void *)k_bwd_items<B, L, F, 1, W, kTileThreads>);
 }
 
 hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_items_max,
@@ -1053,8 +1062,10 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   // outweighs the fewer workgroups per CU (16^3: one instead of two).
   bool wide = kWideGrad && in_lds && g_pay && lds64 + fade_shm + kStatic <= 160 * 1024;
   const size_t lds = wide ? lds64 : lds32;
-  // 3 waves per SIMD when 3 workgroups' LDS fits a CU
+  // 3 waves per SIMD when 3 workgroups' LDS fits a CU; 512-thread workgroups
+  // when only one does
   const bool w3 = !(in_lds && g_pay) || wgs_per_cu(lds) >= 3;
+  bool wide_wg = kWideWorkgroup && in_lds && g_pay && wgs_per_cu(lds) == 1;
   const unsigned grid = (unsigned)std::min<int64_t>(n_items_max, 1 << 20);
   BwdOut out{g_pay, g_pos, g_rot, g_scale};
   size_t shm = (in_lds && g_pay ? lds : 0) + fade_shm;
@@ -1064,7 +1075,7 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   uint32_t sort_cap = 0;
   if (kSortPairs) {
     const size_t wgs = w3 ? 3 : (shm + kStatic <= 80 * 1024 ? 2 : 1);
-    const size_t share = 160 * 1024 / wgs - kStatic;
+    const size_t share = 160 * 1024 / wgs - (wide_wg ? 2 * kStatic : kStatic);   // static LDS grows with the workgroup
     const size_t room = share > shm ? (share - shm) / (sizeof(uint16_t) + 1) : 0;
     const size_t want = (size_t)av.item_entries * kTileThreads;
     sort_cap = (uint32_t)(std::min(room, want) / kTileThreads * kTileThreads);
@@ -1073,16 +1084,17 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   if (shm > 64 * 1024) {
     // allow more than the default dynamic LDS per workgroup (gfx950 has 160 KB)
     const void *fn =
-        bf16 ? (in_lds ? (wide ? (fade ? bwd_items_fn<true, true, true, true>(w3) : bwd_items_fn<true, true, false, true>(w3))
-                               : (fade ? bwd_items_fn<true, true, true, false>(w3) : bwd_items_fn<true, true, false, false>(w3)))
-                       : (fade ? bwd_items_fn<true, false, true, false>(w3) : bwd_items_fn<true, false, false, false>(w3)))
-             : (in_lds ? (wide ? (fade ? bwd_items_fn<false, true, true, true>(w3) : bwd_items_fn<false, true, false, true>(w3))
-                               : (fade ? bwd_items_fn<false, true, true, false>(w3) : bwd_items_fn<false, true, false, false>(w3)))
-                       : (fade ? bwd_items_fn<false, false, true, false>(w3) : bwd_items_fn<false, false, false, false>(w3)));
+        bf16 ? (in_lds ? (wide ? (fade ? bwd_items_fn<true, true, true, true>(w3, wide_wg) : bwd_items_fn<true, true, false, true>(w3, wide_wg))
+                               : (fade ? bwd_items_fn<true, true, true, false>(w3, wide_wg) : bwd_items_fn<true, true, false, false>(w3, wide_wg)))
+                       : (fade ? bwd_items_fn<true, false, true, false>(w3, wide_wg) : bwd_items_fn<true, false, false, false>(w3, wide_wg)))
+             : (in_lds ? (wide ? (fade ? bwd_items_fn<false, true, true, true>(w3, wide_wg) : bwd_items_fn<false, true, false, true>(w3, wide_wg))
+                               : (fade ? bwd_items_fn<false, true, true, false>(w3, wide_wg) : bwd_items_fn<false, true, false, false>(w3, wide_wg)))
+                       : (fade ? bwd_items_fn<false, false, true, false>(w3, wide_wg) : bwd_items_fn<false, false, false, false>(w3, wide_wg)));
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess) {
       (void)hipGetLastError();
       in_lds = false;   // gradients straight to device memory, pairs in list order
       wide = false;
+      wide_wg = false;
       sort_cap = 0;
       shm = fade_shm;
     }
@@ -1091,11 +1103,15 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
 #define MVP_BWD(B, L, F, W)                                                                                   \
   do {                                                                                                        \
     if (w3)                                                                                                   \
-      hipLaunchKernelGGL((k_bwd_items<B, L, F, 3, W>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot,        \
-                         p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, out, sort_cap);              \
+      hipLaunchKernelGGL((k_bwd_items<B, L, F, 3, W, kTileThreads>), dim3(grid), dim3(kTileThreads), shm, s, av, \
+                         p.rot, p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, out, sort_cap);       \
+    else if (wide_wg)                                                                                         \
+      hipLaunchKernelGGL((k_bwd_items<B, L, F, 1, W, 2 * kTileThreads>), dim3(grid), dim3(2 * kTileThreads),    \
+                         shm, s, av, p.rot, p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, out,      \
+                         sort_cap);                                                                           \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_bwd_items<B, L, F, 1, W>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot,        \
-                         p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, out, sort_cap);              \
+      hipLaunchKernelGGL((k_bwd_items<B, L, F, 1, W, kTileThreads>), dim3(grid), dim3(kTileThreads), shm, s, av, \
+                         p.rot, p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, out, sort_cap);       \
   } while (0)
 #define MVP_BWD_F(B, F)                                                                                       \
   do {                                                                                                        \
