@@ -181,8 +181,10 @@ mvp_status mvp_render_fwd(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims 
  * float32, using the aux of the same forward.  ACCUMULATES (+=) into
  *   grad_payload [N,M,M,M,4] float32 (also for bf16 payloads),
  *   grad_pos [N,3], grad_rot [N,3,3], grad_scale [N,3] float32;
- * any of the four may be NULL to skip it.  Uses device atomics, so the order
- * of floating-point additions (not the math) varies between runs. */
+ * any of the four may be NULL to skip it.  A primitive's payload gradient is
+ * summed per work item in FP64 in on-chip memory and then added to grad_payload
+ * with FP32 device atomics, as are the pose gradients, so the order of
+ * floating-point additions (not the math) varies between runs. */
 mvp_status mvp_render_bwd(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims *prims,
                           const mvp_ray_aux *aux, const float *grad_rgba,
                           float *grad_payload, float *grad_pos, float *grad_rot,
