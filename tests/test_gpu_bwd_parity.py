@@ -168,3 +168,24 @@ def test_large_grid_gradients(mvp_ctx, m):
     gpu = _gpu_grads(acc, dp, aux, up.reshape(1, cam.height, cam.width, 4))
     _check(gpu, ref, 1e-4)
     acc.destroy()
+
+
+def test_work_item_beyond_the_ordering_buffer(mvp_ctx):
+    """A work item with more pairs than the LDS left for ordering them replays
+    its pairs in list order.  One 16^3 primitive filling a 128x64 view gives one
+    work item of 32 fully covered tiles, 8192 pairs; with the FP64 gradient
+    copy (131 KB) in a 512-thread workgroup the ordering buffer holds 7936."""
+    rng = np.random.default_rng(95)
+    prims = scenes.Prims(np.zeros((1, 3), np.float32), np.eye(3, dtype=np.float32)[None].copy(),
+                         np.full((1, 3), 1.6, np.float32), scenes.random_payload(rng, 1, 16, 0.8))
+    cam = scenes.axis_camera(128, 64, (0.0, 0.0, 3.0))
+    params = scenes.MarchParams(1 / 32, 1e-4)
+    say("one 16^3 primitive over 128x64 pixels")
+    ref_fwd = oracle.render(prims, cam, params)
+    assert (ref_fwd["rgba"][..., 3] > 0).all()   # every ray of every tile pairs with it
+    up = _upstream(ref_fwd["rgba"].shape, 96, ref_fwd["margin"])
+    _, ref = oracle.render_grad(prims, cam, params, up)
+    acc, dp, rgba, aux = gpu_forward(mvp_ctx, prims, [cam], params)
+    gpu = _gpu_grads(acc, dp, aux, up.reshape(1, cam.height, cam.width, 4))
+    _check(gpu, ref, 1e-4)
+    acc.destroy()
