@@ -608,7 +608,6 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
   const size_t kb = (size_t)k * M3;
   float G0 = 0.f, G1 = 0.f, G2 = 0.f, H0 = 0.f, H1 = 0.f, H2 = 0.f;
   float4 cv[8];
-  float acc[8][4];
   float wq[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) wq[q] = 1.0f;
@@ -631,8 +630,6 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
   int j = jr.x;
   Cell c;
   if (j <= jh) c = locate(A, B, (float)j * dt, M, hM);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
   while (j <= jh) {
     const int cell = c.idx;
     const int ci0 = c.i[0], ci1 = c.i[1], ci2 = c.i[2];
@@ -669,6 +666,18 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
         if (q & bit)
 #pragma unroll
           for (int ch = 0; ch < 4; ++ch) cf[q][ch] -= cf[q ^ bit][ch];
+    // The ray's upstream colour gradient g is fixed along the run, and every
+    // colour term of a sample (g . rgb, the colour adjoint ws g and its
+    // position derivative) involves the colours only through g . c: the run
+    // keeps gcf[q] = g . cf[q][rgb] and the opacity coefficients sf[q], and
+    // sums the colour adjoint as g times sum_s m_q ws.
+    float gcf[8], sf[8], bw[8], b3[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      gcf[q] = g.x * cf[q][0] + g.y * cf[q][1] + g.z * cf[q][2];
+      sf[q] = cf[q][3];
+      bw[q] = b3[q] = 0.f;
+    }
     do {
       const float tau = (float)j * dt;
       const float fx = mx ? 1.0f - c.f[0] : c.f[0];
@@ -676,37 +685,31 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
       const float fz = mz ? 1.0f - c.f[2] : c.f[2];
       const float mxy = fx * fy, mxz = fx * fz, myz = fy * fz, mxyz = mxy * fz;
       const float mq[8] = {1.0f, fx, fy, mxy, fz, mxz, myz, mxyz};
-      float val[4];
+      float gc = gcf[0], sg = sf[0];
 #pragma unroll
-      for (int ch = 0; ch < 4; ++ch) {
-        float v = cf[0][ch];
-#pragma unroll
-        for (int q = 1; q < 8; ++q) v = fmaf(mq[q], cf[q][ch], v);
-        val[ch] = v;
+      for (int q = 1; q < 8; ++q) {
+        gc = fmaf(mq[q], gcf[q], gc);
+        sg = fmaf(mq[q], sf[q], sg);
       }
-      const float gc = g.x * val[0] + g.y * val[1] + g.z * val[2];
       float a3, ws;   // dL/dsigma and the factor of g in dL/d(rgb) for this prim-sample
       if (clamped && j == ax.j_end && (!seq || k >= rcv.kstar)) {
         a3 = seq ? 0.f : wsig * (gc + tdot);
-        ws = seq ? (k == rcv.kstar ? wsig : 0.f) : wsig * val[3];
+        ws = seq ? (k == rcv.kstar ? wsig : 0.f) : wsig * sg;
       } else {
         a3 = dt * (tdot + gc);
-        ws = dt * val[3];
+        ws = dt * sg;
       }
-      const float a0 = ws * g.x, a1 = ws * g.y, a2 = ws * g.z;
       // adjoint of the monomial coefficients; the corners' are formed at the flush
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        acc[q][0] = fmaf(mq[q], a0, acc[q][0]);
-        acc[q][1] = fmaf(mq[q], a1, acc[q][1]);
-        acc[q][2] = fmaf(mq[q], a2, acc[q][2]);
-        acc[q][3] = fmaf(mq[q], a3, acc[q][3]);
+        bw[q] = fmaf(mq[q], ws, bw[q]);
+        b3[q] = fmaf(mq[q], a3, b3[q]);
       }
       // gradient with respect to y of the interpolant of the adjoint-weighted
       // channels: al[q] = a . cf[q], d/dx of sum al[q] m_q, times dx/dy = hM
       float al[8];
 #pragma unroll
-      for (int q = 1; q < 8; ++q) al[q] = a0 * cf[q][0] + a1 * cf[q][1] + a2 * cf[q][2] + a3 * cf[q][3];
+      for (int q = 1; q < 8; ++q) al[q] = fmaf(ws, gcf[q], a3 * sf[q]);
       const float gx = hMx * (al[1] + al[3] * fy + al[5] * fz + al[7] * myz);
       const float gyv = hMy * (al[2] + al[3] * fx + al[6] * fz + al[7] * mxz);
       const float gz = hMz * (al[4] + al[5] * fx + al[6] * fy + al[7] * mxy);
@@ -720,6 +723,14 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
       if (j > jh) break;
       c = locate(A, B, (float)j * dt, M, hM);
     } while (c.idx == cell);
+    float acc[8][4];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      acc[q][0] = g.x * bw[q];
+      acc[q][1] = g.y * bw[q];
+      acc[q][2] = g.z * bw[q];
+      acc[q][3] = b3[q];
+    }
     // monomial adjoint -> corner adjoint (transpose of the basis change)
 #pragma unroll
     for (int bit = 1; bit < 8; bit <<= 1)
@@ -729,8 +740,6 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
 #pragma unroll
           for (int ch = 0; ch < 4; ++ch) acc[q][ch] -= acc[q | bit][ch];
     if (gdst) flush_cell<LDS_ACC, FADE>(gdst, cell, M, acc, wq, 0xffu, m);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.f;
   }
   if (!pose) return;
   // y = A (o + tau d - t), A = diag(1/s) R^T; d is the unit pixel ray
