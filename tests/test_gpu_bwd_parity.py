@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import gpu_forward, oracle_pixels, rel_l2, say
+from gpu_util import check_grads, gpu_forward, oracle_pixels, rel_l2, say
 from paper_2103_01954_amd import scenes
 from paper_2103_01954_amd.api import DevicePrims, render
 
@@ -33,10 +33,7 @@ def _gpu_grads(acc, dp, aux, up):
 
 
 def _check(gpu, ref, tol):
-    for k in GROUPS:
-        e = rel_l2(gpu[k], ref[k])
-        say(f"  {k}: rel-L2 {e:.3e} (|ref| {np.linalg.norm(ref[k]):.3e})")
-        assert e <= tol, k
+    check_grads(gpu, ref, tol, GROUPS)
 
 
 def test_fd_scene_gradients(mvp_ctx):

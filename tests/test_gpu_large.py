@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import gpu_forward, max_abs, oracle_pixels, rel_l2, say
+from gpu_util import check_grads, gpu_forward, max_abs, oracle_pixels, say
 from paper_2103_01954_amd import scenes
 
 pytestmark = pytest.mark.gpu
@@ -49,9 +49,6 @@ def test_large_forward_and_backward_sampled(mvp_ctx, c4):
         ref = gr if ref is None else {k: ref[k] + gr[k] for k in GROUPS}
     grads = acc.render_bwd(dp, aux, torch.from_numpy(up.astype(np.float32)).cuda())
     torch.cuda.synchronize()
-    for k in GROUPS:
-        got = grads[k].cpu().numpy().astype(np.float64).reshape(ref[k].shape)
-        e = rel_l2(got, ref[k])
-        say(f"  {k}: rel-L2 {e:.3e}")
-        assert e <= 1e-4, k
+    got = {k: grads[k].cpu().numpy().astype(np.float64).reshape(ref[k].shape) for k in GROUPS}
+    check_grads(got, ref, 1e-4, GROUPS)
     acc.destroy()
