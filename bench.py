@@ -8,14 +8,25 @@ seeded synthetic data resident in device memory before timing starts.
 
 Prints one JSON line.  `value` is ray-samples (samples inside >= 1
 intersected primitive, up to the early stop) per second of the whole step.
+Beside it: the same 4096-primitive scene forward-only at one 1024^2 view in
+FP32 and BF16, the 32768-primitive 16^3 BF16 workload (2 views of 2048^2,
+forward + backward), the memory traffic of the two march kernels (bytes they
+load and store, counted by the kernels themselves; L2 hit rate and
+L2-to-fabric bytes from rocprofv3 counters collected in child processes on
+this GPU), serving latency, and the FP64 CPU oracle timed on the host cores.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import json
 import multiprocessing as mp
 import os
+import shutil
+import subprocess
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -25,11 +36,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Msamples/s fwd+bwd at 4096 prims, 1024² px; p50/p99 frame latency served"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per prim-sample (FP32 payload): forward gathers 8 corners x
-# 16 B; backward re-gathers them and scatters 8 x 16 B of FP32 gradients
+# Gather model of the method (algorithmic bytes per prim-sample): the forward
+# gathers 8 corners x 4 channels of the payload; the backward gathers them
+# again and scatters 8 x 16 B of FP32 gradients.
 BYTES_FWD = {"f32": 128, "bf16": 64}
 BYTES_BWD = {"f32": 256, "bf16": 192}
-KERN_FWD, KERN_BWD = "k_march_fwd", "k_bwd_items"     # the kernels these bytes are charged to
+KERN_FWD, KERN_BWD = "k_march_fwd", "k_bwd_items"
+VOX = {"f32": 16, "bf16": 8}   # bytes of one voxel (4 channels)
 
 
 def parse():
@@ -41,17 +54,21 @@ def parse():
     ap.add_argument("--views", type=int, default=4)
     ap.add_argument("--bf16", action="store_true", help="BF16 payload (FP32 accumulation)")
     ap.add_argument("--large", action="store_true",
-                    help="the large workload instead: 32768 prims x 16^3 BF16, 2 views 2048^2, step 1/1024")
+                    help="the large workload as the headline: 32768 prims x 16^3 BF16, 2 views 2048^2, step 1/1024")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving latency run")
+    ap.add_argument("--no-extra", action="store_true", help="skip the forward-only and large workloads")
+    ap.add_argument("--no-counters", action="store_true", help="skip the rocprofv3 counter passes")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests per offered load")
     ap.add_argument("--cpu-rows", type=int, default=32)
-    ap.add_argument("--copy-calib-mib", type=int, default=0,
-                    help="after timing, run one plain device copy of this many MiB (reference for "
-                         "rocprofv3 FETCH_SIZE/WRITE_SIZE scaling)")
-    ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"),
-                    help="HBM bytes per launch measured by rocprofv3 counters")
+    ap.add_argument("--profile-child", action="store_true",
+                    help="(internal) one warm-up and one step of the workload, then a 1 GiB device copy; "
+                         "run under rocprofv3 by the counter passes")
     return ap.parse_args()
+
+
+def note(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 # ----------------------------------------------------------------------------
@@ -105,7 +122,238 @@ def cpu_baseline(size, views, n_rows):
 
 
 # ----------------------------------------------------------------------------
-# GPU
+# memory traffic of the march kernels, from the kernels' own load counts
+# ----------------------------------------------------------------------------
+
+def fwd_bytes(lc, dtype, rays, aux=True):
+    """Bytes k_march_fwd loads and stores per launch: voxel-corner sets (8
+    corners), pair intervals (8 B) and pair local rays (pa + pb, 32 B) as
+    counted by the kernel, plus per ray its two list offsets (16 B) and its
+    outputs (rgba 16 B, aux 8 B)."""
+    return (lc["fwd_cells"] * 8 * VOX[dtype] + lc["fwd_pair_intervals"] * 8 + lc["fwd_pair_rays"] * 32
+            + rays * (16 + 16 + (8 if aux else 0)))
+
+
+def bwd_bytes(lc, dtype, pose=True):
+    """Bytes k_bwd_items loads and stores per launch: per pair visited by the
+    ordering pass 28 B (list slot 4, interval 8, ray index 4, the ray's last
+    sample 4, its bounds 8); per pair replayed 84 B (list slot 4, pa 16, pb 16,
+    pj 8, aux 8, upstream gradient 16, ray constants 16) plus 144 B for the pose
+    chain (camera 48, world-to-local rows 48, rotation 36, scale 12); per cell
+    run one voxel-corner set (8 corners); per non-zero gradient value added to
+    device memory 4 B."""
+    return (lc["bwd_pairs_visited"] * 28 + lc["bwd_pairs_replayed"] * (84 + (144 if pose else 0))
+            + lc["bwd_cell_runs"] * 8 * VOX[dtype] + lc["bwd_grad_flush"] * 4)
+
+
+# ----------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------
+
+def workload(name, a=None):
+    """(workload, dtype, description, target or None)."""
+    from paper_2103_01954_amd import scenes
+    if name == "c2":
+        w = scenes.c2(size=a.size, views=a.views)
+        dtype = "bf16" if a.bf16 else "f32"
+        if a.bf16:
+            w.prims = scenes.as_bf16(w.prims)
+        return (w, dtype, f"4096 prims x 8^3 {dtype} payload (noisy sphere, 70% empty voxels), "
+                          f"{a.views} views {a.size}x{a.size}, step 1/512, eps 1e-6, build+fwd+MSE+bwd",
+                w.extra["target"])
+    if name in ("c1_f32", "c1_bf16"):
+        bf16 = name.endswith("bf16")
+        w = scenes.c1(bf16=bf16)
+        dtype = "bf16" if bf16 else "f32"
+        return (w, dtype, f"4096 prims x 8^3 {dtype} payload, 1 view 1024x1024, step 1/512, eps 1e-6, "
+                          f"build+fwd", None)
+    if name == "c4":
+        w = scenes.c4()
+        return (w, "bf16", "32768 prims x 16^3 bf16 payload (noisy sphere, 80% empty voxels), 2 views 2048x2048, "
+                           "step 1/1024, eps 1e-6, build+fwd+MSE+bwd", "random")
+    raise ValueError(name)
+
+
+class Runner:
+    """One workload resident on the device, stepped as build + forward
+    (+ MSE gradient + backward)."""
+
+    def __init__(self, ctx, w, dtype, target, backward=True):
+        import torch
+        from paper_2103_01954_amd.api import DevicePrims
+        self.torch = torch
+        self.ctx, self.w, self.dtype, self.backward = ctx, w, dtype, backward
+        self.dp = DevicePrims.from_host(w.prims, bf16=(dtype == "bf16"))
+        V, H, W = len(w.cams), w.cams[0].height, w.cams[0].width
+        self.rays = V * H * W
+        if backward:
+            if isinstance(target, str):
+                self.target = torch.rand((V, H, W, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(107))
+            else:
+                self.target = torch.from_numpy(target).cuda()
+            self.grads = {"payload": torch.zeros(self.dp.payload.shape, dtype=torch.float32, device="cuda"),
+                          "pos": torch.zeros_like(self.dp.pos), "rot": torch.zeros_like(self.dp.rot),
+                          "scale": torch.zeros_like(self.dp.scale)}
+        self.stream = torch.cuda.current_stream()
+
+    def step(self):
+        acc = self.ctx.build_accel(self.dp, self.w.cams, self.w.params)
+        rgba, aux = acc.render_fwd(self.dp, want_aux=self.backward)
+        if self.backward:
+            g = self.torch.zeros_like(rgba)
+            g[..., :3] = (2.0 / self.target.numel()) * (rgba[..., :3] - self.target)   # d MSE / d I
+            for v in self.grads.values():
+                v.zero_()
+            acc.render_bwd(self.dp, aux, g, self.grads)
+        return acc
+
+    def measure(self, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step().destroy()
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        self.ctx.timing_start(steps)      # HIP events around the march kernels themselves
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start.record(self.stream)
+        last = None
+        for _ in range(steps):
+            acc = self.step()
+            if last is not None:
+                last.destroy()
+            last = acc
+        stop.record(self.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = start.elapsed_time(stop) / steps
+        lc = last.load_counts()
+        info = last.info()
+        last.destroy()
+        fwd_ms = float(np.mean(self.ctx.timing_read("fwd")))
+        bwd_ms = float(np.mean(self.ctx.timing_read("bwd"))) if self.backward else None
+        self.ctx.timing_stop()
+        return {"ms": ms, "wall": wall, "lc": lc, "info": info, "fwd_ms": fwd_ms, "bwd_ms": bwd_ms}
+
+
+def kernel_report(m, dtype, rays, backward):
+    """Per march kernel: milliseconds per launch, bytes it moves per launch
+    (its own load counts), their rate against the HBM peak, and the gather
+    model's rate for comparison."""
+    lc = m["lc"]
+    ps = lc["prim_samples"]
+    out = {}
+    fb = fwd_bytes(lc, dtype, rays, aux=backward)
+    out[KERN_FWD] = {"ms": round(m["fwd_ms"], 3), "bytes": int(fb),
+                     "gbs": round(fb / (m["fwd_ms"] / 1e3) / 1e9, 1),
+                     "frac": round(fb / (m["fwd_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "gather_model_gbs": round(ps * BYTES_FWD[dtype] / (m["fwd_ms"] / 1e3) / 1e9, 1)}
+    if backward:
+        bb = bwd_bytes(lc, dtype)
+        out[KERN_BWD] = {"ms": round(m["bwd_ms"], 3), "bytes": int(bb),
+                         "gbs": round(bb / (m["bwd_ms"] / 1e3) / 1e9, 1),
+                         "frac": round(bb / (m["bwd_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "gather_model_gbs": round(ps * BYTES_BWD[dtype] / (m["bwd_ms"] / 1e3) / 1e9, 1)}
+    return out
+
+
+# ----------------------------------------------------------------------------
+# rocprofv3 counter passes (child processes on this GPU)
+# ----------------------------------------------------------------------------
+
+COUNTER_PASSES = [("l2", ["TCC_HIT_sum", "TCC_MISS_sum"]), ("fetch", ["FETCH_SIZE"]), ("write", ["WRITE_SIZE"])]
+
+
+def _rocprof():
+    for c in (shutil.which("rocprofv3"), "/opt/rocm/bin/rocprofv3"):
+        if c and os.path.exists(c):
+            return c
+    return None
+
+
+def counter_passes(child_args, timeout_s=150):
+    """Run `bench.py --profile-child` under rocprofv3 once per counter pass
+    and return {kernel: {counter: value per dispatch}} for the march kernels and
+    the copy kernel, or an error string."""
+    prof = _rocprof()
+    if prof is None:
+        return None, "rocprofv3 not found"
+    res = {}
+    tmp = tempfile.mkdtemp(prefix="mvp_pmc_", dir="/tmp")
+    try:
+        for tag, counters in COUNTER_PASSES:
+            d = os.path.join(tmp, tag)
+            cmd = [prof, "--pmc", *counters, "-f", "csv", "-d", d, "-o", "run", "--",
+                   sys.executable, os.path.join(ROOT, "bench.py"), "--profile-child", *child_args]
+            env = dict(os.environ, TMPDIR="/tmp")
+            note(f"counters: {' '.join(counters)}")
+            try:
+                r = subprocess.run(cmd, cwd="/tmp", env=env, capture_output=True, text=True, timeout=timeout_s)
+            except subprocess.TimeoutExpired:
+                return None, f"rocprofv3 pass {tag} timed out"
+            files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+            if not files:
+                return None, f"rocprofv3 pass {tag} wrote no counter file (rc {r.returncode}): {r.stderr[-300:]}"
+            for f in files:
+                with open(f) as fh:
+                    for row in csv.DictReader(fh):
+                        name = row.get("Kernel_Name", "")
+                        short = ("copy" if "copyBuffer" in name or "direct_copy" in name else
+                                 KERN_FWD if KERN_FWD in name else KERN_BWD if KERN_BWD in name else None)
+                        if short is None:
+                            continue
+                        cn, cv = row.get("Counter_Name"), float(row.get("Counter_Value", "nan"))
+                        res.setdefault(short, {}).setdefault(cn, []).append(cv)
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    # per dispatch: the march kernels' last dispatch (the step after the warm-up);
+    # for the copy kernels the largest dispatch (the 1 GiB calibration copy)
+    return {k: {c: (max(v) if k == "copy" else v[-1]) for c, v in d.items()} for k, d in res.items()}, None
+
+
+def traffic_report(pmc, copy_bytes, kern_ms):
+    """L2 hit rate and L2-to-fabric bytes (FETCH_SIZE / WRITE_SIZE in KiB per
+    dispatch, each scaled by what the counter reads for a plain device copy of
+    known size) per march kernel."""
+    copy = pmc.get("copy", {})
+    f_scale = copy_bytes / (copy["FETCH_SIZE"] * 1024) if copy.get("FETCH_SIZE") else None
+    w_scale = copy_bytes / (copy["WRITE_SIZE"] * 1024) if copy.get("WRITE_SIZE") else None
+    out = {"fetch_scale": round(f_scale, 4) if f_scale else None,
+           "write_scale": round(w_scale, 4) if w_scale else None}
+    for k in (KERN_FWD, KERN_BWD):
+        d = pmc.get(k)
+        if not d:
+            continue
+        e = {}
+        if "TCC_HIT_sum" in d and "TCC_MISS_sum" in d:
+            e["l2_hit_rate"] = round(d["TCC_HIT_sum"] / max(d["TCC_HIT_sum"] + d["TCC_MISS_sum"], 1.0), 4)
+        if f_scale and w_scale and "FETCH_SIZE" in d and "WRITE_SIZE" in d:
+            b = d["FETCH_SIZE"] * 1024 * f_scale + d["WRITE_SIZE"] * 1024 * w_scale
+            e["l2_fabric_bytes"] = int(b)
+            if kern_ms.get(k):
+                e["l2_fabric_gbs"] = round(b / (kern_ms[k] / 1e3) / 1e9, 1)
+        out[k] = e
+    return out
+
+
+def device_copy(mib, reps):
+    """A plain device-to-device copy of `mib` MiB, `reps` times; returns GB/s
+    (read + write bytes)."""
+    import torch
+    src = torch.empty(mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    return 2.0 * (mib << 20) * reps / (c0.elapsed_time(c1) / 1e3) / 1e9
+
+
+# ----------------------------------------------------------------------------
+# main
 # ----------------------------------------------------------------------------
 
 def main():
@@ -115,119 +363,76 @@ def main():
               "across GPUs, which this build does not launch", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2103_01954_amd import scenes
-    from paper_2103_01954_amd.api import Context, DevicePrims
+    from paper_2103_01954_amd.api import Context
 
-    if a.large:
-        w = scenes.c4()
-        a.bf16, a.size, a.views, a.no_cpu = True, w.cams[0].width, len(w.cams), True
-        target = torch.rand((a.views, a.size, a.size, 3), device="cuda",
-                            generator=torch.Generator("cuda").manual_seed(107))
-        workload = (f"32768 prims x 16^3 bf16 payload (noisy sphere, 80% empty voxels), "
-                    f"{a.views} views {a.size}x{a.size}, step 1/1024, eps 1e-6, build+fwd+MSE+bwd")
-    else:
-        w = scenes.c2(size=a.size, views=a.views)
-        target = torch.from_numpy(w.extra["target"]).cuda()
-    dtype = "bf16" if a.bf16 else "f32"
-    if not a.large:
-        workload = (f"4096 prims x 8^3 {dtype} payload (noisy sphere, 70% empty voxels), "
-                    f"{a.views} views {a.size}x{a.size}, step 1/512, eps 1e-6, build+fwd+MSE+bwd")
-    prims = scenes.as_bf16(w.prims) if a.bf16 and not w.prims.bf16 else w.prims
+    head = "c4" if a.large else "c2"
+    w, dtype, desc, target = workload(head, a)
     ctx = Context(0)
-    dp = DevicePrims.from_host(prims, bf16=a.bf16)
-    grads = {"payload": torch.zeros(dp.payload.shape, dtype=torch.float32, device="cuda"),
-             "pos": torch.zeros_like(dp.pos), "rot": torch.zeros_like(dp.rot),
-             "scale": torch.zeros_like(dp.scale)}
-    stream = torch.cuda.current_stream()
-    n_pix = target.numel()
+    run = Runner(ctx, w, dtype, target, backward=True)
 
-    def step(ev=None):
-        acc = ctx.build_accel(dp, w.cams, w.params)
-        if ev: ev[0].record(stream)
-        rgba, aux = acc.render_fwd(dp)
-        if ev: ev[1].record(stream)
-        g = torch.zeros_like(rgba)
-        g[..., :3] = (2.0 / n_pix) * (rgba[..., :3] - target)      # d MSE / d I
-        for v in grads.values():
-            v.zero_()
-        if ev: ev[2].record(stream)
-        acc.render_bwd(dp, aux, g, grads)
-        if ev: ev[3].record(stream)
-        return acc
+    if a.profile_child:
+        run.step().destroy()
+        torch.cuda.synchronize()
+        run.step().destroy()
+        torch.cuda.synchronize()
+        device_copy(1024, 1)
+        ctx.close()
+        return
 
-    def note(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-    for _ in range(a.warmup):
-        step().destroy()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(a.steps)]
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ctx.timing_start(a.steps)      # HIP events around the march kernels themselves
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record(stream)
-    last = None
-    for i in range(a.steps):
-        acc = step(evs[i])
-        if last is not None:
-            last.destroy()
-        last = acc
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = start.elapsed_time(stop) / a.steps
-    note(f"{a.steps} timed steps: {start.elapsed_time(stop) / a.steps:.3f} ms per step")
-    ray_s, prim_s = last.counts()
-    info = last.info()
-    last.destroy()
-    fwd_call_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    bwd_call_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
-    fwd_ms = float(np.mean(ctx.timing_read("fwd")))
-    bwd_ms = float(np.mean(ctx.timing_read("bwd")))
-    ctx.timing_stop()
+    m = run.measure(a.steps, a.warmup)
+    note(f"{a.steps} timed steps: {m['ms']:.3f} ms per step")
+    lc, ms = m["lc"], m["ms"]
+    ray_s, prim_s = lc["ray_samples"], lc["prim_samples"]
     value = ray_s / (ms / 1e3) / 1e6
+    kr = kernel_report(m, dtype, run.rays, True)
+    del run
+    torch.cuda.empty_cache()
 
-    kern = KERN_BWD if bwd_ms >= fwd_ms else KERN_FWD
-    kms = max(bwd_ms, fwd_ms)
-    per = BYTES_BWD[dtype] if kern == KERN_BWD else BYTES_FWD[dtype]
-    achieved = prim_s * per / (kms / 1e3) / 1e9
+    copy_gbs = device_copy(1024, 5)
+    pmc_err = None
     traffic = None
-    if os.path.exists(a.traffic):
-        try:
-            t = json.load(open(a.traffic))
-            key = f"{kern}:{dtype}:{w.prims.n}:{a.size}x{a.views}"
-            traffic = t.get(key)
-        except Exception:
-            traffic = None
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            # DRAM bytes per launch (rocprofv3, profiles/traffic.json) over the same kernel time
-            "traffic_gbs": round(traffic / (kms / 1e3) / 1e9, 1) if traffic else None, "kernel": kern,
-            "kernel_ms": round(kms, 3), "bytes_per_prim_sample": per,
-            "kernel_ms_each": {KERN_FWD: round(fwd_ms, 3), KERN_BWD: round(bwd_ms, 3)},
-            "call_ms": {"render_fwd": round(fwd_call_ms, 3), "render_bwd": round(bwd_call_ms, 3)},
-            # the whole step (build + forward + backward) against the gather roofline of the
-            # forward's and backward's bytes together: prim-samples/s x bytes / HBM peak
-            "step_gather_frac": round(prim_s / (ms / 1e3) * (BYTES_FWD[dtype] + BYTES_BWD[dtype]) /
-                                      (HBM_PEAK_GBS * 1e9), 4)}
+    if not a.no_counters:
+        child = (["--large"] if a.large else []) + (["--bf16"] if a.bf16 else []) + \
+                ["--size", str(a.size), "--views", str(a.views)]
+        pmc, pmc_err = counter_passes(child)
+        if pmc is not None:
+            # the calibration copy reads 1 GiB and writes 1 GiB
+            traffic = traffic_report(pmc, 1024 << 20, {k: v["ms"] for k, v in kr.items()})
 
-    # a plain device copy: the calibration dispatch for the HBM byte counters
-    # (--copy-calib-mib), and the measured copy bandwidth of this GPU
-    mib = a.copy_calib_mib or 1024
-    src = torch.empty(mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
-    dst = torch.empty_like(src)
-    torch.cuda.synchronize()
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 1 if a.copy_calib_mib else 5
-    c0.record(stream)
-    for _ in range(reps):
-        dst.copy_(src)
-    c1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 2.0 * (mib << 20) * reps / (c0.elapsed_time(c1) / 1e3) / 1e9
-    del src, dst
-    roof["measured_copy_gbs"] = round(copy_gbs, 1)
+    kern = KERN_BWD if kr[KERN_BWD]["ms"] >= kr[KERN_FWD]["ms"] else KERN_FWD
+    k = kr[kern]
+    t_k = (traffic or {}).get(kern, {})
+    roof = {"bound": "hbm", "achieved": k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": k["frac"],
+            "traffic": t_k.get("l2_fabric_bytes"),
+            "kernel": kern, "kernel_ms": k["ms"],
+            "bytes_moved_per_launch": k["bytes"],
+            "what": "bytes the kernel's own loads and stores move (its load counts x their sizes) per launch "
+                    "/ its average launch time (HIP events on its stream), against the 8 TB/s HBM peak; "
+                    "traffic = L2-to-fabric bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by "
+                    "a plain 1 GiB copy; includes Infinity Cache hits)",
+            "kernels": kr, "counters": traffic, "counters_error": pmc_err,
+            "l2_hit_rate": t_k.get("l2_hit_rate"), "l2_fabric_gbs": t_k.get("l2_fabric_gbs"),
+            # the method's gather model (8 corners per prim-sample) over the whole step
+            "gather_model_step_frac": round(prim_s / (ms / 1e3) * (BYTES_FWD[dtype] + BYTES_BWD[dtype]) /
+                                            (HBM_PEAK_GBS * 1e9), 4),
+            "measured_copy_gbs": round(copy_gbs, 1)}
+
+    extra = None
+    if not a.no_extra and not a.large:
+        extra = {}
+        for name, steps, warm, bwd in (("c1_f32", 10, 2, False), ("c1_bf16", 10, 2, False), ("c4", 3, 1, True)):
+            note(f"workload {name}")
+            w2, dt2, desc2, tgt2 = workload(name)
+            r2 = Runner(ctx, w2, dt2, tgt2, backward=bwd)
+            m2 = r2.measure(steps, warm)
+            lc2 = m2["lc"]
+            extra[name] = {"workload": desc2, "ms_per_step": round(m2["ms"], 3),
+                           "msamples_s": round(lc2["ray_samples"] / (m2["ms"] / 1e3) / 1e6, 1),
+                           "mprim_samples_s": round(lc2["prim_samples"] / (m2["ms"] / 1e3) / 1e6, 1),
+                           "ray_samples": lc2["ray_samples"], "prim_samples": lc2["prim_samples"],
+                           "kernels": kernel_report(m2, dt2, r2.rays, bwd)}
+            del r2
+            torch.cuda.empty_cache()
 
     serving = None
     if not a.no_serve:
@@ -253,13 +458,13 @@ def main():
         "metric": METRIC, "value": round(value, 2), "unit": "Msamples/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
-        "config": {"workload": workload,
-                   "global_batch": a.views, "rays": a.views * a.size * a.size},
+        "config": {"workload": desc, "global_batch": len(w.cams), "rays": len(w.cams) * w.cams[0].width *
+                   w.cams[0].height},
         "ray_samples_per_step": ray_s, "prim_samples_per_step": prim_s,
         "mprim_samples_per_s": round(prim_s / (ms / 1e3) / 1e6, 1),
         "prims_per_sample": round(prim_s / max(ray_s, 1), 3),
-        "wall_s_timed": round(wall, 3), "accel": info,
-        "roofline": roof, "cpu_baseline": cpu, "serving": serving,
+        "wall_s_timed": round(m["wall"], 3), "accel": m["info"], "load_counts": lc,
+        "roofline": roof, "workloads": extra, "cpu_baseline": cpu, "serving": serving,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -177,14 +177,22 @@ mvp_status mvp_accel_get_info(const mvp_accel *accel, mvp_accel_info *info);
 mvp_status mvp_render_fwd(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims *prims,
                           float *rgba, mvp_ray_aux *aux, void *stream);
 
-/* Backward of mvp_render_fwd for L with dL/drgba = grad_rgba [n_views,H,W,4]
- * float32, using the aux of the same forward.  ACCUMULATES (+=) into
+/* Backward of mvp_render_fwd (Sec. 3.2.2: the additive accumulation makes the
+ * ray's final state enough to differentiate it, without storing per-sample
+ * values) for L with dL/drgba = grad_rgba [n_views,H,W,4] float32, using the
+ * aux of the same forward: each (ray, primitive) pair is replayed from the
+ * ray's stored last sample and pre-clamp opacity.  ACCUMULATES (+=) into
  *   grad_payload [N,M,M,M,4] float32 (also for bf16 payloads),
  *   grad_pos [N,3], grad_rot [N,3,3], grad_scale [N,3] float32;
  * any of the four may be NULL to skip it.  A primitive's payload gradient is
- * summed per work item in FP64 in on-chip memory and then added to grad_payload
- * with FP32 device atomics, as are the pose gradients, so the order of
- * floating-point additions (not the math) varies between runs. */
+ * summed per work item (up to 64 screen tiles of one primitive) in on-chip
+ * memory as 32-bit fixed point, with a scale chosen per item from a bound on
+ * its contributions so that no sum overflows; each item's sum is then added
+ * to grad_payload with FP32 device atomics, as are the pose gradients, so the
+ * order of those floating-point additions (not the math) varies between runs.
+ * grad_rgba must be finite (a work item whose bound is not finite writes NaN
+ * into its primitive's payload gradient).  Scratch device memory of 24 bytes
+ * per ray comes from the context's memory cache. */
 mvp_status mvp_render_bwd(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims *prims,
                           const mvp_ray_aux *aux, const float *grad_rgba,
                           float *grad_payload, float *grad_pos, float *grad_rot,
@@ -210,6 +218,19 @@ mvp_status mvp_render_bwd_bg(mvp_ctx *ctx, const mvp_accel *accel, const mvp_pri
  * payload fetches). */
 mvp_status mvp_accel_counts(mvp_ctx *ctx, const mvp_accel *accel, uint64_t *ray_samples,
                             uint64_t *prim_samples, void *stream);
+
+/* Load counts of the most recent forward and backward on this structure
+ * (BLOCKS on `stream`), written to the HOST array out[9]:
+ *   [0] ray-samples, [1] prim-samples (as mvp_accel_counts);
+ *   forward: [2] voxel-corner sets loaded (8 corners each), [3] pair-interval
+ *   loads (8 B each), [4] pair local-ray loads (32 B each);
+ *   backward: [5] pairs visited by its ordering pass, [6] pairs replayed,
+ *   [7] cell runs (one voxel-corner set loaded each), [8] non-zero payload
+ *   gradient values added to grad_payload.
+ * The forward's sequential-combine walk over a saturating sample's primitives
+ * is not counted.  Used to express the march kernels' memory traffic in
+ * bytes. */
+mvp_status mvp_accel_load_counts(mvp_ctx *ctx, const mvp_accel *accel, uint64_t *out, void *stream);
 
 /* Hit sets for testing: for every ray, the ids of the primitives its ray
  * intersects (slab test only, including hits with no sample), ascending.
@@ -258,17 +279,30 @@ typedef struct {
 } mvp_request;
 
 /* Queue a request; never blocks.  The scheduler admits queued requests in
- * arrival order as soon as a slot is free and the request's scratch memory
- * fits in the budget, and runs admitted requests concurrently on their slot
- * streams.  A request larger than the whole budget fails at admission. */
+ * arrival order as soon as a slot is free; each slot's worker thread builds
+ * the request's culling structure and launches its forward on the slot's
+ * stream, so builds and marches of different requests overlap on the device.
+ * Scratch memory is reserved against the budget as the build sizes it; a
+ * build that does not fit waits for running requests to finish, and a request
+ * larger than the whole budget fails. */
 mvp_status mvp_submit(mvp_ctx *ctx, const mvp_request *req, uint64_t *ticket);
 
 /* Request state: *state = 0 queued, 1 running, 2 done, 3 failed.  Times are
- * seconds on a monotonic clock (submission, and completion of the GPU work;
- * completion 0 until done).  A done/failed ticket stays queryable until
- * mvp_ticket_release.  Unknown ticket: MVP_ERR_INVALID. */
+ * seconds on the library's monotonic clock (mvp_clock): submission, and
+ * completion of the GPU work (0 until done).  A done/failed ticket stays
+ * queryable until mvp_ticket_release.  Unknown ticket: MVP_ERR_INVALID. */
 mvp_status mvp_poll(mvp_ctx *ctx, uint64_t ticket, int32_t *state, double *t_submit,
                     double *t_done);
+/* The three stamps of a ticket on the mvp_clock clock: submission, the moment
+ * a slot worker began enqueuing the request's culling build on its slot stream
+ * (0 while queued; a request that gave way to an older one for memory is
+ * stamped again when it restarts), and completion of its forward on the
+ * device (0 until done).  Any pointer may be NULL. */
+mvp_status mvp_ticket_times(mvp_ctx *ctx, uint64_t ticket, double *t_submit, double *t_start,
+                            double *t_done);
+/* The monotonic clock (seconds) of the serving stamps, so that a client can
+ * measure latency from its own arrival times. */
+double mvp_clock(void);
 /* Block until the ticket is done or failed, or timeout_s elapses
  * (MVP_ERR_NOT_READY). */
 mvp_status mvp_wait(mvp_ctx *ctx, uint64_t ticket, double timeout_s);

@@ -71,6 +71,7 @@ _SIGS = {
     "mvp_render_fwd_bg": ([P, P, C.POINTER(mvp_prims), P, P, P, P], C.c_int),
     "mvp_render_bwd_bg": ([P, P, C.POINTER(mvp_prims), P, P, P, P, P, P, P, P, P, P], C.c_int),
     "mvp_accel_counts": ([P, P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), P], C.c_int),
+    "mvp_accel_load_counts": ([P, P, C.POINTER(C.c_uint64), P], C.c_int),
     "mvp_debug_hits": ([P, P, C.POINTER(mvp_prims), P, P, C.c_int64, C.POINTER(C.c_int64), P], C.c_int),
     "mvp_timing_start": ([P, C.c_int32], C.c_int),
     "mvp_timing_read": ([P, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_int32)], C.c_int),
@@ -80,6 +81,9 @@ _SIGS = {
     "mvp_scene_release": ([P, C.c_uint64], C.c_int),
     "mvp_submit": ([P, C.POINTER(mvp_request), C.POINTER(C.c_uint64)], C.c_int),
     "mvp_poll": ([P, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+    "mvp_ticket_times": ([P, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                          C.POINTER(C.c_double)], C.c_int),
+    "mvp_clock": ([], C.c_double),
     "mvp_wait": ([P, C.c_uint64, C.c_double], C.c_int),
     "mvp_ticket_release": ([P, C.c_uint64], C.c_int),
 }

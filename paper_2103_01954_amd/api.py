@@ -228,6 +228,16 @@ class Accel:
                                                                   C.byref(b), _stream(stream)))
         return a.value, b.value
 
+    LOAD_COUNT_NAMES = ("ray_samples", "prim_samples", "fwd_cells", "fwd_pair_intervals", "fwd_pair_rays",
+                        "bwd_pairs_visited", "bwd_pairs_replayed", "bwd_cell_runs", "bwd_grad_flush")
+
+    def load_counts(self, stream=None) -> dict:
+        """Load counts of the latest forward and backward (mvp_accel_load_counts)."""
+        buf = (C.c_uint64 * len(self.LOAD_COUNT_NAMES))()
+        L.check("mvp_accel_load_counts", self.ctx.lib.mvp_accel_load_counts(self.ctx.handle, self.handle, buf,
+                                                                            _stream(stream)))
+        return {k: int(buf[i]) for i, k in enumerate(self.LOAD_COUNT_NAMES)}
+
     def debug_hits(self, prims: DevicePrims, stream=None):
         """Per-ray sorted hit sets as (offsets [R+1] int64, ids int32) numpy arrays."""
         R = int(np.prod(self.ray_shape))

@@ -302,7 +302,7 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   MVP_CHECK(keep.get(&a->xf, 3 * (size_t)N));
   MVP_CHECK(keep.get(&a->tile_off, ntile + 1));
   MVP_CHECK(keep.get(&a->ray_off, R + 1));
-  MVP_CHECK(keep.get(&a->counters, 2));
+  MVP_CHECK(keep.get(&a->counters, kNumCounters));
   MVP_CHECK(temp.get(&rect, (size_t)n_views * N));
   MVP_CHECK(temp.get(&tile_cnt, ntile));
   MVP_CHECK(temp.get(&ray_cnt, R));
@@ -546,7 +546,7 @@ static mvp_status render_fwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *
   MVP_CHECK(check_render(ctx, a, prims));
   if (!rgba && a->n_slots > 0) { set_error("rgba is NULL"); return MVP_ERR_INVALID; }
   MVP_HIP(hipSetDevice(ctx->device));
-  MVP_HIP(launch_zero_u64((uint64_t *)a->counters, 2, s));
+  MVP_HIP(launch_zero_u64((uint64_t *)a->counters, kCntFwdPab + 1, s));
   const auto ev = timer_slot(ctx, MVP_KERNEL_FWD_MARCH);
   if (ev.first) MVP_HIP(hipEventRecord(ev.first, s));
   MVP_HIP(launch_march_fwd(a->view(prims->M), *prims, bg, rgba, aux, a->counters, s));
@@ -561,11 +561,11 @@ static mvp_status render_bwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *
   if ((!aux || !grad_rgba) && a->n_slots > 0) { set_error("aux and grad_rgba are required"); return MVP_ERR_INVALID; }
   MVP_HIP(hipSetDevice(ctx->device));
   Blocks temp{ctx, s};
-  mvp::RayConst *rc = nullptr;
-  MVP_CHECK(temp.get(&rc, a->n_rays()));
+  uint8_t *scratch = nullptr;
+  MVP_CHECK(temp.get(&scratch, bwd_scratch_bytes(a->n_rays())));
   const auto ev = timer_slot(ctx, MVP_KERNEL_BWD_MARCH);
-  MVP_HIP(launch_march_bwd(a->view(prims->M), *prims, a->n_items_max, aux, grad_rgba, bg, rgba, rc, grad_payload,
-                           grad_pos, grad_rot, grad_scale, grad_bg, s, ev.first, ev.second));
+  MVP_HIP(launch_march_bwd(a->view(prims->M), *prims, a->n_items_max, aux, grad_rgba, bg, rgba, scratch, grad_payload,
+                           grad_pos, grad_rot, grad_scale, grad_bg, a->counters, s, ev.first, ev.second));
   return MVP_OK;   // the scratch is recycled after the kernels have run
 }
 
@@ -606,6 +606,15 @@ mvp_status mvp_accel_counts(mvp_ctx *ctx, const mvp_accel *a, uint64_t *ray_samp
   MVP_HIP(hipStreamSynchronize(s));
   *ray_samples = h[0];
   *prim_samples = h[1];
+  return MVP_OK;
+}
+
+mvp_status mvp_accel_load_counts(mvp_ctx *ctx, const mvp_accel *a, uint64_t *out, void *stream) {
+  if (!ctx || !a || a->ctx != ctx || !out) { set_error("bad argument"); return MVP_ERR_INVALID; }
+  hipStream_t s = (hipStream_t)stream;
+  MVP_HIP(hipSetDevice(ctx->device));
+  MVP_HIP(hipMemcpyAsync(out, a->counters, kNumCounters * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  MVP_HIP(hipStreamSynchronize(s));
   return MVP_OK;
 }
 

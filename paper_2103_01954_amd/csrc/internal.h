@@ -43,6 +43,21 @@ struct RayConst {
   int32_t kstar, pad;
 };
 
+// Bounds on what one (ray, primitive) pair can add to any single payload
+// gradient value (one voxel, one channel): at most per_sample for each of its
+// replayed samples, plus clamp once if the pair holds the ray's clamping
+// sample.  The backward sums them per work item to choose the fixed-point
+// scale of its on-chip gradient accumulator.
+struct RayBound {
+  float per_sample, clamp;
+};
+
+// Scratch of one backward call over R rays: RayConst [R], RayBound [R] and
+// the payload's largest colour and opacity magnitudes (2 x uint32, float bits).
+__host__ __device__ constexpr size_t bwd_scratch_bytes(size_t R) {
+  return ((R * sizeof(RayConst) + R * sizeof(RayBound) + 8 + 255) / 256) * 256;
+}
+
 struct AccelView {
   int32_t V, W, H, N, M;
   int32_t tiles_x, tiles_y;
@@ -142,6 +157,21 @@ __device__ __forceinline__ void slot_pixel(const AccelView &av, size_t slot, int
   *py = (int)(r / av.W);
 }
 
+// Per-structure counters (uint64), written by the most recent forward (the
+// first five) and backward (the last four) on the structure.
+enum : int {
+  kCntRaySamples = 0,   // samples inside >= 1 primitive, up to the stop
+  kCntPrimSamples = 1,  // (sample, primitive) pairs: trilinear fetches
+  kCntFwdCells = 2,     // forward: voxel-corner sets loaded (8 corners each)
+  kCntFwdPj = 3,        // forward: pair-interval loads (8 B each)
+  kCntFwdPab = 4,       // forward: pair local-ray loads (pa + pb, 32 B each)
+  kCntBwdVisit = 5,     // backward: pairs visited by the ordering / bound pass
+  kCntBwdReplay = 6,    // backward: pairs replayed
+  kCntBwdRuns = 7,      // backward: cell runs (voxel-corner sets loaded)
+  kCntBwdFlush = 8,     // backward: non-zero gradient values added to device memory
+  kNumCounters = 9
+};
+
 // ---- launchers (return the first HIP error) --------------------------------
 hipError_t launch_zero_u32(uint32_t *p, size_t n, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t *p, size_t n, hipStream_t s);
@@ -180,11 +210,13 @@ hipError_t launch_hit_emit(const AccelView &av, int mode, int32_t *tkey, uint32_
 // bg: optional background [rays,3] composited under the premultiplied colour
 hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, const float *bg, float *rgba,
                             mvp_ray_aux *aux, unsigned long long *counters, hipStream_t s);
-// backward; rc is scratch of one RayConst per ray; bg/rgba/g_bg for a composited forward
+// backward; scratch holds bwd_scratch_bytes(n_slots) bytes (nothing in it needs
+// to start at zero); bg/rgba/g_bg for a composited forward
 hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_items_max,
                             const mvp_ray_aux *aux, const float *grad_rgba, const float *bg,
-                            const float *rgba, RayConst *rc, float *g_pay, float *g_pos, float *g_rot,
-                            float *g_scale, float *g_bg, hipStream_t s, hipEvent_t t0 = nullptr,
+                            const float *rgba, void *scratch, float *g_pay, float *g_pos, float *g_rot,
+                            float *g_scale, float *g_bg, unsigned long long *counters, hipStream_t s,
+                            hipEvent_t t0 = nullptr,
                             hipEvent_t t1 = nullptr);   // optional events around the per-pair kernel
 
 }  // namespace mvp

@@ -28,10 +28,12 @@
 // entries (screen tile, primitive) of one primitive: channel adjoints go to
 // the 8 voxel corners with the trilinear weights, accumulated in registers
 // over a run of samples in one cell and then in an LDS copy of the
-// primitive's gradient (FP64 when it fits: LDS FP64 atomic adds run far
-// faster than FP32 ones on gfx950), which is added to device memory once per
-// item; the pose gradient (through y = A (o + t d - pos)) is reduced over the
-// workgroup.
+// primitive's gradient held in 32-bit fixed point (LDS integer atomic adds run
+// about 40 times faster than FP32 ones on gfx950, and integer sums do not
+// depend on the order of the additions), which is added to device memory once
+// per item; the pose gradient (through y = A (o + t d - pos)) is reduced over
+// the workgroup.  The fixed-point scale of an item is chosen from a bound on
+// what its pairs can add to any one gradient value, so no sum can overflow.
 //
 // Built with -ffp-contract=off; fused multiply-adds are written explicitly.
 #include <hip/hip_runtime.h>
@@ -62,16 +64,6 @@ constexpr bool kRotateFlush = true;
 #endif
 constexpr bool kSortPairs = MVP_SORT_PAIRS;
 constexpr int kLenBuckets = 64;
-// The LDS copy of a primitive's payload gradient may be held in FP64.
-#ifndef MVP_WIDE_GRAD
-#define MVP_WIDE_GRAD 1
-#endif
-constexpr bool kWideGrad = MVP_WIDE_GRAD;
-// 512-thread backward workgroups when the LDS gradient leaves room for one.
-#ifndef MVP_WIDE_WG
-#define MVP_WIDE_WG 1
-#endif
-constexpr bool kWideWorkgroup = MVP_WIDE_WG;
 
 template <bool BF16>
 struct Voxels;
@@ -189,8 +181,10 @@ __device__ __forceinline__ int prim_of(const float4 &A) { return __float_as_int(
 // w(i) = exp(-alpha |x_i|^beta), x_i = -1 + 2i/(M-1); W(ix,iy,iz) = w(ix) w(iy) w(iz).
 __device__ __forceinline__ void fill_fade(float *tab, int M, float alpha, float beta) {
   for (int i = threadIdx.x; i < M; i += blockDim.x) {
-    const float x = -1.0f + 2.0f * (float)i / (float)(M - 1);
-    tab[i] = expf(-alpha * powf(fabsf(x), beta));
+    const float x = fabsf(-1.0f + 2.0f * (float)i / (float)(M - 1));
+    // |x|^beta (beta > 0) as exp2(beta log2 |x|), all in FP32
+    const float xb = x > 0.0f ? exp2f(beta * log2f(x)) : 0.0f;
+    tab[i] = expf(-alpha * xb);
   }
 }
 
@@ -242,11 +236,12 @@ __device__ __forceinline__ uint64_t next_by_id(const AccelView &av, uint64_t e0,
   return be;
 }
 
-// Accumulated state of one ray.
+// Accumulated state of one ray, with its counts of samples and of loads
+// (voxel-corner sets, pair intervals pj, pair local rays pa + pb).
 struct RayState {
   float T = 0.f, I0 = 0.f, I1 = 0.f, I2 = 0.f, t_prev = -1.0f;
   int j_end = -1;
-  unsigned long long n_ray = 0, n_prim = 0;
+  uint32_t n_ray = 0, n_prim = 0, n_cell = 0, n_pj = 0, n_pab = 0;
 };
 
 // One clamped additive step with the summed density sig and summed
@@ -322,6 +317,7 @@ __device__ void march_ray(const AccelView &av, const void *pay, const float *fad
   const size_t M3 = (size_t)M * M * M;
   uint64_t e0 = beg;           // pairs before e0 have ended before the window
   int J = av.pj[beg].x;
+  ++st.n_pj;
   while (true) {
     float as[kWin], ar[kWin], ag[kWin], ab[kWin];
     int cnt[kWin];
@@ -333,11 +329,13 @@ __device__ void march_ray(const AccelView &av, const void *pay, const float *fad
     const int J1 = J + kWin;
     for (uint64_t e = e0; e < end; ++e) {
       const int2 r = av.pj[e];
+      ++st.n_pj;
       if (r.x >= J1) break;
       if (r.y < J) continue;
       const int lo = max(r.x, J) - J, hi = min(r.y, J1 - 1) - J;
       const float4 A = av.pa[e];
       const float4 B = av.pb[e];
+      ++st.n_pab;
       const size_t kb = (size_t)prim_of(A) * M3;
       int cur = -1;
       float4 v[8];
@@ -348,6 +346,7 @@ __device__ void march_ray(const AccelView &av, const void *pay, const float *fad
           const Cell c = locate(A, B, tau, M, hM);
           if (c.idx != cur) {
             load_corners<BF16>(pay, kb + c.idx, M, v);
+            ++st.n_cell;
             if (FADE) {
               float wq[8];
               corner_fade(fade, c, wq);
@@ -380,9 +379,14 @@ __device__ void march_ray(const AccelView &av, const void *pay, const float *fad
     if (stop) break;
     // next occupied sample: every pair in front of e0 ends before J1, and all
     // later pairs start no earlier than e0 does
-    while (e0 < end && av.pj[e0].y < J1) ++e0;
+    while (e0 < end) {
+      ++st.n_pj;
+      if (av.pj[e0].y >= J1) break;
+      ++e0;
+    }
     if (e0 == end) break;
     J = max(J1, av.pj[e0].x);
+    ++st.n_pj;
   }
 }
 
@@ -432,11 +436,11 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3)
     if (aux) aux[ray] = mvp_ray_aux{st.j_end, st.t_prev};
   }
   if (counters) {
-    const unsigned long long nr = wave_sum_u64(st.n_ray);
-    const unsigned long long np = wave_sum_u64(st.n_prim);
-    if ((threadIdx.x & (kWave - 1)) == 0 && nr) {
-      atomicAdd(&counters[0], nr);
-      atomicAdd(&counters[1], np);
+    const unsigned long long c[5] = {wave_sum_u64(st.n_ray), wave_sum_u64(st.n_prim), wave_sum_u64(st.n_cell),
+                                     wave_sum_u64(st.n_pj), wave_sum_u64(st.n_pab)};
+    if ((threadIdx.x & (kWave - 1)) == 0 && c[3]) {
+#pragma unroll
+      for (int i = 0; i < 5; ++i) atomicAdd(&counters[i], c[i]);
     }
   }
 }
@@ -471,12 +475,24 @@ hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, const float
 // arithmetic; then Tdot = -g . c_k*, the weight is 1 - T* and kstar = k*.
 // With a background B the output colour is I + (1 - A) B: the upstream of A
 // becomes dL/dA - g . B, and dL/dB = (1 - A) g is accumulated here.
+//
+// Also the ray's bounds for the fixed-point accumulation (RayBound): a replayed
+// sample adds to one gradient value of a corner at most its trilinear weight
+// (<= 1) times dL/dsigma_k or dL/dc_k.  Away from the clamp
+// |dL/dsigma_k| <= dt (|Tdot| + |g|_1 Cmax) and |dL/dc_k| <= dt sigma_max |g|_inf
+// (Cmax, sigma_max: the payload's largest colour and opacity magnitudes; the
+// fade window only lowers them); at the clamping sample dL/dsigma_k has the
+// weight (1 - T_{S-1}) / sigma_S < dt in place of dt and the colour adjoint is
+// at most |g|_inf (sum rule: (1 - T_{S-1}) sigma_k / sigma_S <= 1; sequential:
+// 1 - T* <= 1).
 template <bool BF16, bool FADE>
 __global__ __launch_bounds__(256) void k_bwd_rays(AccelView av, const void *__restrict__ pay,
                                                   const mvp_ray_aux *__restrict__ aux,
                                                   const float4 *__restrict__ grad_rgba,
                                                   const float *__restrict__ bg, const float4 *__restrict__ rgba,
-                                                  RayConst *__restrict__ rc, float *__restrict__ g_bg, size_t R) {
+                                                  RayConst *__restrict__ rc, RayBound *__restrict__ rbd,
+                                                  const uint32_t *__restrict__ pmax, float *__restrict__ g_bg,
+                                                  size_t R) {
   extern __shared__ float s_fade[];
   if (FADE) {
     fill_fade(s_fade, av.M, av.fade_alpha, av.fade_beta);
@@ -534,6 +550,34 @@ __global__ __launch_bounds__(256) void k_bwd_rays(AccelView av, const void *__re
     }
   }
   rc[r] = RayConst{tdot, wsig, kstar, 0};
+  const float cmax = __uint_as_float(pmax[0]), smax = __uint_as_float(pmax[1]);
+  const float g1 = fabsf(g.x) + fabsf(g.y) + fabsf(g.z);
+  const float gi = fmaxf(fabsf(g.x), fmaxf(fabsf(g.y), fabsf(g.z)));
+  const bool clamped = ax.j_end >= 0 && ax.t_prev >= 0.f && (!av.combine || kstar >= 0);
+  rbd[r] = RayBound{av.step * (fabsf(tdot) + g1 * cmax + smax * gi), clamped ? gi : 0.f};
+}
+
+// Largest colour and opacity magnitudes of the payload, as float bits in
+// pmax[0] and pmax[1] (which start at zero; non-negative floats order like
+// their bit patterns).
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_payload_bound(const void *__restrict__ pay, size_t n_vox,
+                                                       uint32_t *__restrict__ pmax) {
+  float c = 0.f, sg = 0.f;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox; i += (size_t)gridDim.x * blockDim.x) {
+    const float4 v = Voxels<BF16>::load(pay, i);
+    c = fmaxf(c, fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z))));
+    sg = fmaxf(sg, fabsf(v.w));
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    c = fmaxf(c, __shfl_xor(c, d, kWave));
+    sg = fmaxf(sg, __shfl_xor(sg, d, kWave));
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicMax(&pmax[0], __float_as_uint(c));
+    atomicMax(&pmax[1], __float_as_uint(sg));
+  }
 }
 
 struct BwdOut {
@@ -548,14 +592,15 @@ struct BwdOut {
 __host__ __device__ __forceinline__ size_t lds_plane(int M) { return (size_t)M * M * M + 1; }
 
 // Add the register-accumulated gradients of one cell to the LDS copy of the
-// primitive's gradient (LDS_ACC, planar) or straight to device memory
-// ([voxel][channel]).  Register slot q holds corner q ^ m of the cell (corner
-// r = dx + 2 dy + 4 dz); `slots` selects the slots to add.  With the fade
-// window the opacity gradient of a stored voxel is the window times the
+// primitive's gradient (LDS_ACC: planar int32 fixed point, value * scale
+// rounded to the nearest integer) or straight to device memory
+// ([voxel][channel], FP32).  Register slot q holds corner q ^ m of the cell
+// (corner r = dx + 2 dy + 4 dz); `slots` selects the slots to add.  With the
+// fade window the opacity gradient of a stored voxel is the window times the
 // gradient of its windowed value.
 template <bool LDS_ACC, bool FADE, typename T>
 __device__ __forceinline__ void flush_cell(T *dst, size_t cell, int M, const float (&acc)[8][4],
-                                           const float (&wq)[8], unsigned slots, unsigned m) {
+                                           const float (&wq)[8], unsigned slots, unsigned m, float scale) {
   const size_t MM = (size_t)M * M;
   const size_t plane = lds_plane(M);
 #pragma unroll
@@ -565,10 +610,10 @@ __device__ __forceinline__ void flush_cell(T *dst, size_t cell, int M, const flo
     const size_t vox = cell + (r & 1u) + ((r >> 1) & 1u) * (size_t)M + (r >> 2) * MM;
     const float a3 = FADE ? acc[q][3] * wq[q] : acc[q][3];
     if constexpr (LDS_ACC) {
-      atomicAdd(dst + vox, (T)acc[q][0]);
-      atomicAdd(dst + plane + vox, (T)acc[q][1]);
-      atomicAdd(dst + 2 * plane + vox, (T)acc[q][2]);
-      atomicAdd(dst + 3 * plane + vox, (T)a3);
+      atomicAdd(dst + vox, __float2int_rn(acc[q][0] * scale));
+      atomicAdd(dst + plane + vox, __float2int_rn(acc[q][1] * scale));
+      atomicAdd(dst + 2 * plane + vox, __float2int_rn(acc[q][2] * scale));
+      atomicAdd(dst + 3 * plane + vox, __float2int_rn(a3 * scale));
     } else {
       unsafeAtomicAdd(dst + vox * 4, acc[q][0]);
       unsafeAtomicAdd(dst + vox * 4 + 1, acc[q][1]);
@@ -587,7 +632,8 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
                                          const float *__restrict__ scale, const void *__restrict__ pay,
                                          const mvp_ray_aux *__restrict__ aux, const float4 *__restrict__ grad_rgba,
                                          const RayConst *__restrict__ rc, uint32_t e, int k, GAcc *gdst,
-                                         const float *s_fade, bool pose, float (&P)[15]) {
+                                         float fxs, const float *s_fade, bool pose, float (&P)[15],
+                                         uint32_t &runs) {
   const int M = av.M;
   const float hM = 0.5f * (float)(M - 1);
   const size_t M3 = (size_t)M * M * M;
@@ -633,6 +679,7 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
   while (j <= jh) {
     const int cell = c.idx;
     const int ci0 = c.i[0], ci1 = c.i[1], ci2 = c.i[2];
+    ++runs;
     {
       const ptrdiff_t b0 = (ptrdiff_t)(kb + cell) + so0;
 #pragma unroll
@@ -739,7 +786,7 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
         if (!(q & bit))
 #pragma unroll
           for (int ch = 0; ch < 4; ++ch) acc[q][ch] -= acc[q | bit][ch];
-    if (gdst) flush_cell<LDS_ACC, FADE>(gdst, cell, M, acc, wq, 0xffu, m);
+    if (gdst) flush_cell<LDS_ACC, FADE>(gdst, cell, M, acc, wq, 0xffu, m, fxs);
   }
   if (!pose) return;
   // y = A (o + tau d - t), A = diag(1/s) R^T; d is the unit pixel ray
@@ -784,10 +831,31 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
 
 
 // Samples the backward replays for pair e: its samples up to the ray's last.
-__device__ __forceinline__ int pair_len(const AccelView &av, const mvp_ray_aux *__restrict__ aux, uint32_t e) {
+// Adds the pair's bound on what it contributes to any one payload gradient
+// value to `bound` (see RayBound).
+__device__ __forceinline__ int pair_len(const AccelView &av, const mvp_ray_aux *__restrict__ aux,
+                                        const RayBound *__restrict__ rbd, uint32_t e, float &bound) {
   const int2 jr = av.pj[e];
-  const int je = aux[__float_as_int(av.pb[e].w)].j_end;
-  return max(0, min(jr.y, je) - jr.x + 1);
+  const int ray = __float_as_int(av.pb[e].w);
+  const int je = aux[ray].j_end;
+  const int n = max(0, min(jr.y, je) - jr.x + 1);
+  if (n > 0) {
+    const RayBound rb = rbd[ray];
+    bound += (float)n * rb.per_sample + (jr.y >= je ? rb.clamp : 0.f);
+  }
+  return n;
+}
+
+// Fixed-point scale of a work item whose pairs add at most `bound` to any one
+// gradient value: with twice that margin every single contribution and every
+// sum stays below 2^30 in magnitude.  0 for a non-finite bound (the item's
+// gradient is then written as NaN).
+__device__ __forceinline__ float fixed_scale(float bound) {
+  if (!(bound < INFINITY)) return 0.0f;
+  if (!(bound > 0.0f)) return 1.0f;
+  int e;
+  (void)frexpf(2.0f * bound, &e);   // 2 bound = m 2^e, 0.5 <= m < 1
+  return ldexpf(1.0f, min(max(30 - e, -126), 126));
 }
 
 // Length classes for ordering pairs: exact below 32 samples, then 4 wide.
@@ -796,32 +864,32 @@ __device__ __forceinline__ int len_bucket(int n) { return n < 32 ? n : min(kLenB
 // Backward, one workgroup per work item: up to kItemEntries culling-list
 // entries (tile, primitive k) of one primitive.  The pairs of those entries
 // (at most one per ray of each tile) are spread over the workgroup's threads;
-// the payload gradient of k is accumulated in LDS (LDS_ACC; in FP64 when
-// WIDE) and added to device memory once per item, the pose gradient is
-// reduced over the workgroup and added with 15 atomics.
+// the payload gradient of k is accumulated in LDS (LDS_ACC, int32 fixed point
+// with the item's scale) and added to device memory once per item, the pose
+// gradient is reduced over the workgroup and added with 15 atomics.
 //
 // WAVES > 1 asks the compiler for that many waves per SIMD (it then keeps the
 // kernel within 512 / WAVES registers, spilling a few); it is used when the
-// LDS gradient leaves room for that many workgroups per CU.  THREADS is the
-// workgroup size: 512 when the LDS gradient leaves room for one workgroup per
-// CU, so that the CU still runs two waves per SIMD.
-template <bool BF16, bool LDS_ACC, bool FADE, int WAVES, bool WIDE, int THREADS>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_bwd_items(
-    AccelView av, const float *__restrict__ rot,
-                                                             const float *__restrict__ scale,
-                                                             const void *__restrict__ pay,
-                                                             const mvp_ray_aux *__restrict__ aux,
-                                                             const float4 *__restrict__ grad_rgba,
-                                                             const RayConst *__restrict__ rc, BwdOut out,
-                                                             uint32_t sort_cap) {
-  // gradient (LDS_ACC; FP64 when WIDE), fade window (FADE), pair order and classes
-  extern __shared__ double s_dyn[];
-  using GAcc = typename std::conditional<LDS_ACC && WIDE, double, float>::type;
+// LDS gradient leaves room for that many workgroups per CU.
+template <bool BF16, bool LDS_ACC, bool FADE, int WAVES>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_bwd_items(
+    AccelView av, const float *__restrict__ rot, const float *__restrict__ scale, const void *__restrict__ pay,
+    const mvp_ray_aux *__restrict__ aux, const float4 *__restrict__ grad_rgba, const RayConst *__restrict__ rc,
+    const RayBound *__restrict__ rbd, BwdOut out, uint32_t sort_cap, unsigned long long *__restrict__ counters) {
+  constexpr int THREADS = kTileThreads;
+  // loads of this thread: pairs visited by the ordering / bound pass, pairs
+  // replayed, their cell runs (one voxel-corner set each), and the non-zero
+  // gradient values it adds to device memory at the end of an item
+  uint32_t n_visit = 0, n_rep = 0, n_run = 0, n_nz = 0;
+  // gradient (LDS_ACC), fade window (FADE), pair order and classes
+  extern __shared__ int s_dyn[];
+  using GAcc = typename std::conditional<LDS_ACC, int, float>::type;
   __shared__ uint32_t s_live;
   __shared__ uint32_t s_cls[kLenBuckets];
   __shared__ uint32_t s_base[2][kLenBuckets];
   __shared__ uint32_t s_wcnt[2][THREADS / kWave][kLenBuckets];
   __shared__ float s_pose[THREADS / kWave][16];
+  __shared__ float s_bnd[THREADS / kWave];
   __shared__ uint64_t s_start[kItemEntries];
   __shared__ uint32_t s_pre[kItemEntries + 1];
   __shared__ int s_prim;
@@ -883,15 +951,17 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
     float P[15];
 #pragma unroll
     for (int i = 0; i < 15; ++i) P[i] = 0.f;
+    float bound = 0.f;   // this thread's pairs' share of the item's bound
+    float fscale = 1.0f;
     if (kSortPairs && total <= sort_cap) {
       // Counting sort of the item's pairs by length class, longest first, in a
       // fixed order (class, then round r = the r-th pair of every thread's
       // contiguous chunk, then wave, then lane), so the replay order, and with
       // it every rounding, is the same from run to run; pairs of one class that
       // are replayed together come from rays a chunk apart.  A histogram pass
-      // and a scan give the class bases; the scatter ranks each round by ballot
-      // within a wave and by per-wave counts across waves (double-buffered, one
-      // barrier per round).
+      // (which also sums the pairs' bounds) and a scan give the class bases;
+      // the scatter ranks each round by ballot within a wave and by per-wave
+      // counts across waves (double-buffered, one barrier per round).
       const uint32_t per = (total + THREADS - 1) / THREADS;
       const uint32_t c0 = threadIdx.x * per, c1 = min(total, c0 + per);
       int q0 = 0;
@@ -906,12 +976,20 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
       __syncthreads();
       for (uint32_t i = c0, q = q0; i < c1; ++i) {
         while (s_pre[q + 1] <= i) ++q;
-        const int n = pair_len(av, aux, av.entry_pairs[s_start[q] + (i - s_pre[q])]);
+        const int n = pair_len(av, aux, rbd, av.entry_pairs[s_start[q] + (i - s_pre[q])], bound);
+        ++n_visit;
         const int b = n > 0 ? len_bucket(n) : 0xff;
         s_pcls[i] = (uint8_t)b;
         if (n > 0) atomicAdd(&s_cls[b], 1u);
       }
+#pragma unroll
+      for (int d = kWave / 2; d > 0; d >>= 1) bound += __shfl_xor(bound, d, kWave);
+      if (lane == 0) s_bnd[wave] = bound;
       __syncthreads();
+      bound = 0.f;
+#pragma unroll
+      for (int w = 0; w < THREADS / kWave; ++w) bound += s_bnd[w];
+      fscale = fixed_scale(bound);
       if (wave == 0) {   // exclusive scan over the classes from the longest down
         const uint32_t c = s_cls[kLenBuckets - 1 - lane];
         uint32_t incl = c;
@@ -966,30 +1044,50 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
           if (s_pre[mid] <= i) q = mid; else hi = mid - 1;
         }
         const uint32_t e = av.entry_pairs[s_start[q] + (i - s_pre[q])];
-        bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, e, k, gdst, s_fade, pose, P);
+        bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, e, k, gdst, fscale, s_fade, pose, P,
+                                      n_run);
+        ++n_rep;
       }
     } else {
-    // list order (more pairs than the ordering buffer holds).
-    // kChunkedPairs: each thread replays a contiguous run of the flattened
-    // pairs, so the lanes of a wave follow rays some pixels apart, which flush
-    // into different voxel cells at once; otherwise pair i goes to thread
-    // i mod 256 (neighbouring pixels on neighbouring lanes).
-    const uint32_t per = kChunkedPairs ? (total + THREADS - 1) / THREADS : 1;
-    const uint32_t stride = kChunkedPairs ? 1 : THREADS;
-    uint32_t i = kChunkedPairs ? threadIdx.x * per : threadIdx.x;
-    const uint32_t iend = kChunkedPairs ? min(total, i + per) : total;
-    if (i < iend) {
-      int q = 0, hi = nent - 1;    // entry of flattened pair i: last q with s_pre[q] <= i
-      while (q < hi) {
-        const int mid = (q + hi + 1) >> 1;
-        if (s_pre[mid] <= i) q = mid; else hi = mid - 1;
+      // list order (more pairs than the ordering buffer holds).
+      // kChunkedPairs: each thread replays a contiguous run of the flattened
+      // pairs, so the lanes of a wave follow rays some pixels apart, which flush
+      // into different voxel cells at once; otherwise pair i goes to thread
+      // i mod 256 (neighbouring pixels on neighbouring lanes).
+      const uint32_t per = kChunkedPairs ? (total + THREADS - 1) / THREADS : 1;
+      const uint32_t stride = kChunkedPairs ? 1 : THREADS;
+      const uint32_t i0 = kChunkedPairs ? threadIdx.x * per : threadIdx.x;
+      const uint32_t iend = kChunkedPairs ? min(total, i0 + per) : total;
+      int q0 = 0;
+      if (i0 < iend) {
+        int hi = nent - 1;    // entry of flattened pair i0: last q with s_pre[q] <= i0
+        while (q0 < hi) {
+          const int mid = (q0 + hi + 1) >> 1;
+          if (s_pre[mid] <= i0) q0 = mid; else hi = mid - 1;
+        }
       }
-      for (; i < iend; i += stride) {
+      if (LDS_ACC && out.pay) {   // the item's bound, for the fixed-point scale
+        for (uint32_t i = i0, q = q0; i < iend; i += stride) {
+          while (s_pre[q + 1] <= i) ++q;
+          (void)pair_len(av, aux, rbd, av.entry_pairs[s_start[q] + (i - s_pre[q])], bound);
+          ++n_visit;
+        }
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) bound += __shfl_xor(bound, d, kWave);
+        if (lane == 0) s_bnd[wave] = bound;
+        __syncthreads();
+        bound = 0.f;
+#pragma unroll
+        for (int w = 0; w < THREADS / kWave; ++w) bound += s_bnd[w];
+        fscale = fixed_scale(bound);
+      }
+      for (uint32_t i = i0, q = q0; i < iend; i += stride) {
         while (s_pre[q + 1] <= i) ++q;
         const uint32_t e = av.entry_pairs[s_start[q] + (i - s_pre[q])];
-        bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, e, k, gdst, s_fade, pose, P);
+        bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, e, k, gdst, fscale, s_fade, pose, P,
+                                      n_run);
+        ++n_rep;
       }
-    }
     }
     if (pose) {
 #pragma unroll
@@ -1017,74 +1115,96 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
     if (LDS_ACC && out.pay && total > 0) {
       float *dst = out.pay + M3 * 4 * (size_t)k;
       const size_t plane = lds_plane(M);
+      const bool ok = fscale > 0.0f;
+      const float inv = ok ? 1.0f / fscale : __builtin_nanf("");   // exact: a power of two
       for (int i = threadIdx.x; i < nacc; i += THREADS) {   // device order: voxel i/4, channel i%4
-        const float x = (float)s_grad[(i & 3) * plane + (i >> 2)];
-        if (x != 0.f) unsafeAtomicAdd(dst + i, x);
+        const GAcc v = s_grad[(i & 3) * plane + (i >> 2)];
+        if (v != 0 || !ok) {
+          unsafeAtomicAdd(dst + i, (float)v * inv);
+          ++n_nz;
+        }
       }
     }
     __syncthreads();   // LDS is reused by the next item
   }
+  if (counters) {
+    const unsigned long long c[4] = {wave_sum_u64(n_visit), wave_sum_u64(n_rep), wave_sum_u64(n_run),
+                                     wave_sum_u64(n_nz)};
+    if (lane == 0 && (c[0] | c[1] | c[3])) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) atomicAdd(&counters[kCntBwdVisit + i], c[i]);
+    }
+  }
 }
 
 // Largest planar LDS copy of a primitive's gradient (4 planes of M^3 + 1
-// floats): up to M = 16.
+// int32 values): up to M = 16.
 constexpr size_t kLdsGradBytes = 64 * 1024 + 16;
 
-template <bool B, bool L, bool F, bool W>
-static const void *bwd_items_fn(bool w3, bool wide_wg) {
-  return w3 ? (const void *)k_bwd_items<B, L, F, 3, W, kTileThreads>
-            : (wide_wg ? (const void *)k_bwd_items<B, L, F, 1, W, 2 * kTileThreads>
-                       : (const void *)k_bwd_items<B, L, F, 1, W, kTileThreads>);
+template <bool B, bool L, bool F>
+static const void *bwd_items_fn(bool w3) {
+  return w3 ? (const void *)k_bwd_items<B, L, F, 3> : (const void *)k_bwd_items<B, L, F, 1>;
 }
 
 hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_items_max,
                             const mvp_ray_aux *aux, const float *grad_rgba, const float *bg,
-                            const float *rgba, RayConst *rc, float *g_pay, float *g_pos, float *g_rot,
-                            float *g_scale, float *g_bg, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+                            const float *rgba, void *scratch, float *g_pay, float *g_pos, float *g_rot,
+                            float *g_scale, float *g_bg, unsigned long long *counters, hipStream_t s,
+                            hipEvent_t t0, hipEvent_t t1) {
   const size_t R = (size_t)av.n_slots;
+  if (counters) {
+    const hipError_t ez = launch_zero_u64((uint64_t *)counters + kCntBwdVisit, 4, s);
+    if (ez != hipSuccess) return ez;
+  }
   if (R == 0) return hipSuccess;
+  RayConst *rc = (RayConst *)scratch;
+  RayBound *rbd = (RayBound *)(rc + R);
+  uint32_t *pmax = (uint32_t *)(rbd + R);
   const bool bf16 = p.payload_dtype == MVP_BF16;
   const bool fade = av.fade_alpha > 0.f;
   const size_t fade_shm = fade ? (size_t)p.M * sizeof(float) : 0;
+  hipError_t e = launch_zero_u32(pmax, 2, s);
+  if (e != hipSuccess) return e;
+  const size_t n_vox = (size_t)p.n_prim * p.M * p.M * p.M;
+  if (n_vox) {
+    const unsigned pg = (unsigned)std::min<size_t>((n_vox + 255) / 256, 2048);
+    if (bf16)
+      hipLaunchKernelGGL((k_payload_bound<true>), dim3(pg), dim3(256), 0, s, p.payload, n_vox, pmax);
+    else
+      hipLaunchKernelGGL((k_payload_bound<false>), dim3(pg), dim3(256), 0, s, p.payload, n_vox, pmax);
+  }
   const unsigned rb = (unsigned)((R + 255) / 256);
 #define MVP_RAYS(B, F)                                                                                        \
   hipLaunchKernelGGL((k_bwd_rays<B, F>), dim3(rb), dim3(256), fade_shm, s, av, p.payload, aux,               \
-                     (const float4 *)grad_rgba, bg, (const float4 *)rgba, rc, g_bg, R)
+                     (const float4 *)grad_rgba, bg, (const float4 *)rgba, rc, rbd, pmax, g_bg, R)
   if (bf16) {
     if (fade) MVP_RAYS(true, true); else MVP_RAYS(true, false);
   } else {
     if (fade) MVP_RAYS(false, true); else MVP_RAYS(false, false);
   }
 #undef MVP_RAYS
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess || p.n_prim == 0 || n_items_max == 0) return e;
-  const size_t lds32 = lds_plane(p.M) * 4 * sizeof(float), lds64 = lds_plane(p.M) * 4 * sizeof(double);
-  bool in_lds = lds32 <= kLdsGradBytes;
+  const size_t lds = lds_plane(p.M) * 4 * sizeof(int);
+  bool in_lds = g_pay && lds <= kLdsGradBytes;
   const size_t kStatic = 4096;   // the kernel's static LDS is under 4 KB
   auto wgs_per_cu = [&](size_t grad) {
     for (int w = 3; w > 1; --w)
       if ((size_t)w * (grad + fade_shm + kStatic) <= 160 * 1024) return w;
     return 1;
   };
-  // The LDS gradient is held in FP64 whenever it fits: on gfx950 an LDS FP64
-  // atomic add sustains about 20 times the lane rate of an FP32 one, which
-  // outweighs the fewer workgroups per CU (16^3: one instead of two).
-  bool wide = kWideGrad && in_lds && g_pay && lds64 + fade_shm + kStatic <= 160 * 1024;
-  const size_t lds = wide ? lds64 : lds32;
-  // 3 waves per SIMD when 3 workgroups' LDS fits a CU; 512-thread workgroups
-  // when only one does
-  const bool w3 = !(in_lds && g_pay) || wgs_per_cu(lds) >= 3;
-  bool wide_wg = kWideWorkgroup && in_lds && g_pay && wgs_per_cu(lds) == 1;
+  // 3 waves per SIMD when 3 workgroups' LDS fits a CU
+  const bool w3 = !in_lds || wgs_per_cu(lds) >= 3;
   const unsigned grid = (unsigned)std::min<int64_t>(n_items_max, 1 << 20);
   BwdOut out{g_pay, g_pos, g_rot, g_scale};
-  size_t shm = (in_lds && g_pay ? lds : 0) + fade_shm;
+  size_t shm = (in_lds ? lds : 0) + fade_shm;
   // the pair-ordering buffer takes what is left of the LDS share of a
   // workgroup at the occupancy chosen above (items with more pairs than it
   // holds keep their pairs in list order)
   uint32_t sort_cap = 0;
   if (kSortPairs) {
     const size_t wgs = w3 ? 3 : (shm + kStatic <= 80 * 1024 ? 2 : 1);
-    const size_t share = 160 * 1024 / wgs - (wide_wg ? 2 * kStatic : kStatic);   // static LDS grows with the workgroup
+    const size_t share = 160 * 1024 / wgs - kStatic;
     const size_t room = share > shm ? (share - shm) / (sizeof(uint16_t) + 1) : 0;
     const size_t want = (size_t)av.item_entries * kTileThreads;
     sort_cap = (uint32_t)(std::min(room, want) / kTileThreads * kTileThreads);
@@ -1093,40 +1213,31 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   if (shm > 64 * 1024) {
     // allow more than the default dynamic LDS per workgroup (gfx950 has 160 KB)
     const void *fn =
-        bf16 ? (in_lds ? (wide ? (fade ? bwd_items_fn<true, true, true, true>(w3, wide_wg) : bwd_items_fn<true, true, false, true>(w3, wide_wg))
-                               : (fade ? bwd_items_fn<true, true, true, false>(w3, wide_wg) : bwd_items_fn<true, true, false, false>(w3, wide_wg)))
-                       : (fade ? bwd_items_fn<true, false, true, false>(w3, wide_wg) : bwd_items_fn<true, false, false, false>(w3, wide_wg)))
-             : (in_lds ? (wide ? (fade ? bwd_items_fn<false, true, true, true>(w3, wide_wg) : bwd_items_fn<false, true, false, true>(w3, wide_wg))
-                               : (fade ? bwd_items_fn<false, true, true, false>(w3, wide_wg) : bwd_items_fn<false, true, false, false>(w3, wide_wg)))
-                       : (fade ? bwd_items_fn<false, false, true, false>(w3, wide_wg) : bwd_items_fn<false, false, false, false>(w3, wide_wg)));
+        bf16 ? (in_lds ? (fade ? bwd_items_fn<true, true, true>(w3) : bwd_items_fn<true, true, false>(w3))
+                       : (fade ? bwd_items_fn<true, false, true>(w3) : bwd_items_fn<true, false, false>(w3)))
+             : (in_lds ? (fade ? bwd_items_fn<false, true, true>(w3) : bwd_items_fn<false, true, false>(w3))
+                       : (fade ? bwd_items_fn<false, false, true>(w3) : bwd_items_fn<false, false, false>(w3)));
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess) {
       (void)hipGetLastError();
       in_lds = false;   // gradients straight to device memory, pairs in list order
-      wide = false;
-      wide_wg = false;
       sort_cap = 0;
       shm = fade_shm;
     }
   }
   if (t0) (void)hipEventRecord(t0, s);
-#define MVP_BWD(B, L, F, W)                                                                                   \
-  do {                                                                                                        \
-    if (w3)                                                                                                   \
-      hipLaunchKernelGGL((k_bwd_items<B, L, F, 3, W, kTileThreads>), dim3(grid), dim3(kTileThreads), shm, s, av, \
-                         p.rot, p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, out, sort_cap);       \
-    else if (wide_wg)                                                                                         \
-      hipLaunchKernelGGL((k_bwd_items<B, L, F, 1, W, 2 * kTileThreads>), dim3(grid), dim3(2 * kTileThreads),    \
-                         shm, s, av, p.rot, p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, out,      \
-                         sort_cap);                                                                           \
-    else                                                                                                      \
-      hipLaunchKernelGGL((k_bwd_items<B, L, F, 1, W, kTileThreads>), dim3(grid), dim3(kTileThreads), shm, s, av, \
-                         p.rot, p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, out, sort_cap);       \
+#define MVP_BWD(B, L, F)                                                                                       \
+  do {                                                                                                         \
+    if (w3)                                                                                                    \
+      hipLaunchKernelGGL((k_bwd_items<B, L, F, 3>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale, \
+                         p.payload, aux, (const float4 *)grad_rgba, rc, rbd, out, sort_cap, counters);        \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_bwd_items<B, L, F, 1>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale, \
+                         p.payload, aux, (const float4 *)grad_rgba, rc, rbd, out, sort_cap, counters);        \
   } while (0)
-#define MVP_BWD_F(B, F)                                                                                       \
-  do {                                                                                                        \
-    if (in_lds && wide) MVP_BWD(B, true, F, true);                                                            \
-    else if (in_lds) MVP_BWD(B, true, F, false);                                                              \
-    else MVP_BWD(B, false, F, false);                                                                         \
+#define MVP_BWD_F(B, F)                                  \
+  do {                                                   \
+    if (in_lds) MVP_BWD(B, true, F);                     \
+    else MVP_BWD(B, false, F);                           \
   } while (0)
   if (bf16) {
     if (fade) MVP_BWD_F(true, true); else MVP_BWD_F(true, false);

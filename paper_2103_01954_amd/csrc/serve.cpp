@@ -1,14 +1,18 @@
 // Serving: resident scenes and continuous batching of render requests.
 //
-// Requests are queued by mvp_submit and admitted in arrival order by one
-// scheduler thread.  A request is admitted when one of the slots (each owning
-// a HIP stream) is free and its device memory fits in the budget; memory is
-// reserved in three steps as the request's culling structure is sized (fixed
-// buffers, tile lists, ray/primitive pairs).  If a step does not fit, the
-// scheduler keeps completing finished requests until it does, so requests of
-// different sizes flow through as memory frees up.  Admitted requests render
-// concurrently on their slot streams, overlapping on the device with each
-// other and with the next request's culling build.  A host callback enqueued
+// Requests are queued by mvp_submit and admitted in arrival order by a
+// scheduler thread, which hands each one to a free slot.  Every slot owns a
+// HIP stream and a worker thread that builds the request's culling structure
+// and launches its forward march on that stream, so the builds of different
+// requests (with their host round trips) and the marches of admitted requests
+// all overlap on the device.  Device memory is reserved against the budget in
+// three steps as the build sizes the structure (fixed buffers, tile lists,
+// ray/primitive pairs).  A build whose next step does not fit waits while
+// other requests are running; when none is running, the oldest waiting build
+// keeps its memory and younger builds give theirs back and return to the
+// front of the queue, so builds cannot wait on each other forever; a request
+// that does not fit even alone fails.  While a build waits for memory no new
+// build starts (admission stays in arrival order).  A host callback enqueued
 // behind each request's forward stamps its completion time.
 #include <hip/hip_runtime.h>
 
@@ -16,13 +20,14 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <thread>
 
 #include "ctx.h"
 
 namespace mvp {
 
-static double now_s() {
+double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
@@ -33,7 +38,7 @@ class Server {
   mvp_status scene_create(const mvp_prims *src, uint64_t *id);
   mvp_status scene_release(uint64_t id);
   mvp_status submit(const mvp_request *r, uint64_t *ticket);
-  mvp_status poll(uint64_t t, int32_t *state, double *ts, double *td);
+  mvp_status poll(uint64_t t, int32_t *state, double *ts, double *tstart, double *td);
   mvp_status wait(uint64_t t, double timeout_s);
   mvp_status ticket_release(uint64_t t);
   size_t budget() const { return budget_; }
@@ -48,48 +53,59 @@ class Server {
   struct Ticket {
     mvp_request req{};
     int32_t state = 0;   // 0 queued, 1 running, 2 done, 3 failed
-    double t_submit = 0, t_done = 0;
+    double t_submit = 0, t_start = 0, t_done = 0;
   };
+  enum : int { kFree = 0, kBuilding = 1, kRunning = 2 };
   struct Slot {
     Server *srv = nullptr;
     hipStream_t stream = nullptr;
-    bool busy = false;
+    int state = kFree;                 // guarded by mu_
+    bool has_work = false;             // a ticket handed over, not yet picked up (mu_)
+    bool waiting = false;              // its build waits for memory (mu_)
     std::atomic<bool> finished{false};
     double t_finish = 0;
     uint64_t ticket = 0;
     mvp_accel *accel = nullptr;
     size_t reserved = 0;
+    std::thread worker;
   };
   static void host_done(void *p);
   static mvp_status admit_cb(void *user, size_t bytes);
   void run();
+  void work(Slot &slot);
   bool reap_locked();
-  void start_locked(Slot &slot, uint64_t t, std::unique_lock<std::mutex> &lk);
+  void release_slot_locked(Slot &slot);
 
   mvp_ctx *ctx_;
   size_t budget_;
-  size_t used_ = 0;   // resident scenes + reservations of running requests
-  std::vector<Slot> slots_;
+  size_t used_ = 0;   // resident scenes + reservations of building and running requests
+  std::vector<std::unique_ptr<Slot>> slots_;
   std::mutex mu_;
-  std::condition_variable cv_;        // scheduler wake-ups
+  std::condition_variable cv_;        // scheduler and admission wake-ups
+  std::condition_variable work_cv_;   // slot workers
   std::condition_variable done_cv_;   // ticket completions
   std::deque<uint64_t> queue_;
   std::unordered_map<uint64_t, Ticket> tickets_;
   std::unordered_map<uint64_t, Scene> scenes_;
   uint64_t next_ticket_ = 1, next_scene_ = 1;
   bool stop_ = false;
-  Slot *building_ = nullptr;          // slot whose build is asking for memory
   hipStream_t copy_stream_ = nullptr; // scene uploads
   std::thread thread_;
 };
 
-Server::Server(mvp_ctx *ctx, size_t budget, int n_slots) : ctx_(ctx), budget_(budget), slots_(n_slots) {
+Server::Server(mvp_ctx *ctx, size_t budget, int n_slots) : ctx_(ctx), budget_(budget) {
   (void)hipSetDevice(ctx->device);
-  for (auto &s : slots_) {
+  for (int i = 0; i < n_slots; ++i) {
+    slots_.emplace_back(new Slot());
+    Slot &s = *slots_.back();
     s.srv = this;
     (void)hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
   }
   (void)hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking);
+  for (auto &s : slots_) {
+    Slot *sp = s.get();
+    s->worker = std::thread([this, sp] { work(*sp); });
+  }
   thread_ = std::thread([this] { run(); });
 }
 
@@ -99,13 +115,15 @@ Server::~Server() {
     stop_ = true;
   }
   cv_.notify_all();
-  thread_.join();
+  thread_.join();     // returns once the queue is empty and every slot is free
+  work_cv_.notify_all();
+  for (auto &s : slots_) s->worker.join();
   (void)hipSetDevice(ctx_->device);
   for (auto &s : slots_) {
-    if (s.stream) {
-      (void)hipStreamSynchronize(s.stream);
-      if (s.accel) destroy_accel(ctx_, s.accel, s.stream);
-      (void)hipStreamDestroy(s.stream);
+    if (s->stream) {
+      (void)hipStreamSynchronize(s->stream);
+      if (s->accel) destroy_accel(ctx_, s->accel, s->stream);
+      (void)hipStreamDestroy(s->stream);
     }
   }
   for (auto &kv : scenes_) ctx_->arena.release_after(kv.second.blocks, copy_stream_);
@@ -122,11 +140,21 @@ void Server::host_done(void *p) {
   srv->cv_.notify_all();
 }
 
+void Server::release_slot_locked(Slot &slot) {
+  if (slot.accel) destroy_accel(ctx_, slot.accel, slot.stream);
+  slot.accel = nullptr;
+  used_ -= slot.reserved;
+  slot.reserved = 0;
+  slot.state = kFree;
+  slot.finished.store(false);
+}
+
 // complete finished requests; returns true if any slot was freed
 bool Server::reap_locked() {
   bool any = false;
-  for (auto &s : slots_) {
-    if (!s.busy || !s.finished.load()) continue;
+  for (auto &sp : slots_) {
+    Slot &s = *sp;
+    if (s.state != kRunning || !s.finished.load()) continue;
     auto it = tickets_.find(s.ticket);
     if (it != tickets_.end()) {
       it->second.state = 2;
@@ -134,81 +162,108 @@ bool Server::reap_locked() {
       auto sc = scenes_.find(it->second.req.scene_id);
       if (sc != scenes_.end()) --sc->second.pending;
     }
-    if (s.accel) destroy_accel(ctx_, s.accel, s.stream);
-    s.accel = nullptr;
-    used_ -= s.reserved;
-    s.reserved = 0;
-    s.busy = false;
-    s.finished.store(false);
+    release_slot_locked(s);
     any = true;
   }
-  if (any) done_cv_.notify_all();
+  if (any) {
+    done_cv_.notify_all();
+    cv_.notify_all();
+  }
   return any;
 }
 
-// Called (with mu_ held by the scheduler) before each group of allocations of
-// the build in progress.  Waits for running requests to finish while the
-// bytes do not fit; fails if nothing else is running and they still do not.
+// Called (from a slot worker, without the lock) before each group of
+// allocations of the build in progress.  MVP_ERR_BUSY tells the build to give
+// way to an older one (see the top of the file).
 mvp_status Server::admit_cb(void *user, size_t bytes) {
-  Server *srv = (Server *)user;
+  Slot *me = (Slot *)user;
+  Server *srv = me->srv;
   std::unique_lock<std::mutex> lk(srv->mu_);
-  Slot *me = srv->building_;
   while (srv->used_ + bytes > srv->budget_) {
-    bool others = false;
-    for (auto &s : srv->slots_)
-      if (s.busy && &s != me) others = true;
-    if (!others) {
-      set_error("request needs %zu bytes beyond the serving budget (%zu of %zu in use)", bytes, srv->used_,
-                srv->budget_);
-      return MVP_ERR_OOM;
+    bool running = false, older_waiting = false, younger = false;
+    for (auto &sp : srv->slots_) {
+      const Slot &s = *sp;
+      if (&s == me) continue;
+      if (s.state == kRunning) running = true;
+      if (s.state == kBuilding && s.ticket < me->ticket && s.waiting) older_waiting = true;
+      if (s.state == kBuilding && s.ticket > me->ticket) younger = true;
+    }
+    if (!running && older_waiting) {
+      me->waiting = false;
+      set_error("build gives way to an older request waiting for memory");
+      return MVP_ERR_BUSY;
+    }
+    if (!running && !younger && !older_waiting) {
+      bool older = false;
+      for (auto &sp : srv->slots_)
+        if (sp.get() != me && sp->state == kBuilding) older = true;
+      if (!older) {
+        me->waiting = false;
+        set_error("request needs %zu bytes beyond the serving budget (%zu of %zu in use)", bytes, srv->used_,
+                  srv->budget_);
+        return MVP_ERR_OOM;
+      }
+    }
+    if (!me->waiting) {
+      me->waiting = true;
+      srv->cv_.notify_all();   // builds of other slots re-check who waits
     }
     if (!srv->reap_locked()) srv->cv_.wait_for(lk, std::chrono::microseconds(200));
   }
+  me->waiting = false;
   srv->used_ += bytes;
   me->reserved += bytes;
   return MVP_OK;
 }
 
-void Server::start_locked(Slot &slot, uint64_t t, std::unique_lock<std::mutex> &lk) {
-  Ticket &tk = tickets_[t];
-  tk.state = 1;
-  slot.busy = true;
-  slot.ticket = t;
-  slot.reserved = 0;
-  slot.finished.store(false);
-  const mvp_request req = tk.req;
-  auto sc = scenes_.find(req.scene_id);
-  const mvp_prims prims = sc->second.prims;
-  building_ = &slot;
-  lk.unlock();
-  Admit admit{&Server::admit_cb, this};
-  mvp_accel *a = nullptr;
-  mvp_status st = build_accel(ctx_, &prims, &req.cam, 1, &req.params, nullptr, 0, &a, slot.stream, &admit);
-  if (st == MVP_OK) {
-    slot.accel = a;
-    hipError_t e = launch_zero_u64((uint64_t *)a->counters, 2, slot.stream);
-    if (e == hipSuccess) e = launch_march_fwd(a->view(prims.M), prims, nullptr, req.rgba_out, nullptr, a->counters, slot.stream);
-    if (e == hipSuccess) e = hipLaunchHostFunc(slot.stream, &Server::host_done, &slot);
-    if (e != hipSuccess) {
-      set_error("launch failed: %s", hipGetErrorString(e));
-      st = MVP_ERR_DEVICE;
+// Slot worker: build the handed-over request and launch its forward.
+void Server::work(Slot &slot) {
+  (void)hipSetDevice(ctx_->device);
+  std::unique_lock<std::mutex> lk(mu_);
+  while (true) {
+    work_cv_.wait(lk, [&] { return slot.has_work || stop_; });
+    if (!slot.has_work) break;   // stopping
+    slot.has_work = false;
+    const uint64_t t = slot.ticket;
+    Ticket &tk = tickets_[t];
+    tk.t_start = now_s();
+    const mvp_request req = tk.req;
+    const mvp_prims prims = scenes_.find(req.scene_id)->second.prims;
+    lk.unlock();
+    Admit admit{&Server::admit_cb, &slot};
+    mvp_accel *a = nullptr;
+    mvp_status st = build_accel(ctx_, &prims, &req.cam, 1, &req.params, nullptr, 0, &a, slot.stream, &admit);
+    if (st == MVP_OK) {
+      slot.accel = a;
+      hipError_t e = launch_zero_u64((uint64_t *)a->counters, kCntFwdPab + 1, slot.stream);
+      if (e == hipSuccess)
+        e = launch_march_fwd(a->view(prims.M), prims, nullptr, req.rgba_out, nullptr, a->counters, slot.stream);
+      if (e == hipSuccess) e = hipLaunchHostFunc(slot.stream, &Server::host_done, &slot);
+      if (e != hipSuccess) {
+        set_error("launch failed: %s", hipGetErrorString(e));
+        st = MVP_ERR_DEVICE;
+      }
     }
-  }
-  lk.lock();
-  building_ = nullptr;
-  if (st != MVP_OK) {
-    // failed request: release what it holds and report it
-    (void)hipStreamSynchronize(slot.stream);
-    if (slot.accel) destroy_accel(ctx_, slot.accel, slot.stream);
-    slot.accel = nullptr;
-    used_ -= slot.reserved;
-    slot.reserved = 0;
-    slot.busy = false;
-    tk.state = 3;
-    tk.t_done = now_s();
-    auto sc2 = scenes_.find(req.scene_id);   // the map may have rehashed meanwhile
-    if (sc2 != scenes_.end()) --sc2->second.pending;
-    done_cv_.notify_all();
+    if (st != MVP_OK) (void)hipStreamSynchronize(slot.stream);
+    lk.lock();
+    slot.waiting = false;
+    Ticket &tk2 = tickets_[t];   // the map may have rehashed meanwhile
+    if (st == MVP_OK) {
+      slot.state = kRunning;
+    } else if (st == MVP_ERR_BUSY) {
+      // gave way to an older build: back to the front of the queue
+      release_slot_locked(slot);
+      tk2.state = 0;
+      queue_.push_front(t);
+    } else {
+      release_slot_locked(slot);
+      tk2.state = 3;
+      tk2.t_done = now_s();
+      auto sc = scenes_.find(req.scene_id);
+      if (sc != scenes_.end()) --sc->second.pending;
+      done_cv_.notify_all();
+    }
+    cv_.notify_all();
   }
 }
 
@@ -217,18 +272,25 @@ void Server::run() {
   std::unique_lock<std::mutex> lk(mu_);
   while (true) {
     reap_locked();
-    if (stop_) {
-      bool busy = false;
-      for (auto &s : slots_) busy |= s.busy;
-      if (!busy && queue_.empty()) break;
-    }
+    bool busy = false, blocked = false;
     Slot *free_slot = nullptr;
-    for (auto &s : slots_)
-      if (!s.busy) { free_slot = &s; break; }
-    if (free_slot && !queue_.empty()) {
+    for (auto &sp : slots_) {
+      Slot &s = *sp;
+      busy |= s.state != kFree || s.has_work;
+      blocked |= s.waiting;
+      if (!free_slot && s.state == kFree && !s.has_work) free_slot = &s;
+    }
+    if (stop_ && !busy && queue_.empty()) break;
+    if (free_slot && !blocked && !queue_.empty()) {
       const uint64_t t = queue_.front();
       queue_.pop_front();
-      start_locked(*free_slot, t, lk);
+      tickets_[t].state = 1;
+      free_slot->state = kBuilding;
+      free_slot->ticket = t;
+      free_slot->reserved = 0;
+      free_slot->finished.store(false);
+      free_slot->has_work = true;
+      work_cv_.notify_all();
       continue;
     }
     cv_.wait_for(lk, std::chrono::milliseconds(5));
@@ -321,12 +383,13 @@ mvp_status Server::submit(const mvp_request *r, uint64_t *ticket) {
   return MVP_OK;
 }
 
-mvp_status Server::poll(uint64_t t, int32_t *state, double *ts, double *td) {
+mvp_status Server::poll(uint64_t t, int32_t *state, double *ts, double *tstart, double *td) {
   std::lock_guard<std::mutex> g(mu_);
   auto it = tickets_.find(t);
   if (it == tickets_.end()) { set_error("unknown ticket %llu", (unsigned long long)t); return MVP_ERR_INVALID; }
   if (state) *state = it->second.state;
   if (ts) *ts = it->second.t_submit;
+  if (tstart) *tstart = it->second.t_start;
   if (td) *td = it->second.t_done;
   return MVP_OK;
 }
@@ -399,8 +462,15 @@ mvp_status mvp_submit(mvp_ctx *ctx, const mvp_request *req, uint64_t *ticket) {
 
 mvp_status mvp_poll(mvp_ctx *ctx, uint64_t ticket, int32_t *state, double *t_submit, double *t_done) {
   if (!ctx || !ctx->server) { set_error("no serving state"); return MVP_ERR_INVALID; }
-  return ctx->server->poll(ticket, state, t_submit, t_done);
+  return ctx->server->poll(ticket, state, t_submit, nullptr, t_done);
 }
+
+mvp_status mvp_ticket_times(mvp_ctx *ctx, uint64_t ticket, double *t_submit, double *t_start, double *t_done) {
+  if (!ctx || !ctx->server) { set_error("no serving state"); return MVP_ERR_INVALID; }
+  return ctx->server->poll(ticket, nullptr, t_submit, t_start, t_done);
+}
+
+double mvp_clock(void) { return now_s(); }
 
 mvp_status mvp_wait(mvp_ctx *ctx, uint64_t ticket, double timeout_s) {
   if (!ctx || !ctx->server) { set_error("no serving state"); return MVP_ERR_INVALID; }

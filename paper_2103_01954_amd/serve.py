@@ -54,6 +54,16 @@ class Server:
                                                   C.byref(b)))
         return s.value, a.value, b.value
 
+    def times(self, ticket: int):
+        """(t_submit, t_start, t_done) of a ticket on the library clock (mvp_clock)."""
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        L.check("mvp_ticket_times", self.ctx.lib.mvp_ticket_times(self.ctx.handle, C.c_uint64(ticket), C.byref(a),
+                                                                  C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def clock(self) -> float:
+        return float(self.ctx.lib.mvp_clock())
+
     def wait(self, ticket: int, timeout_s: float = 60.0) -> int:
         return self.ctx.lib.mvp_wait(self.ctx.handle, C.c_uint64(ticket), float(timeout_s))
 
@@ -63,41 +73,63 @@ class Server:
 
 @dataclass
 class Result:
-    latency_ms: List[float]
+    latency_ms: List[float]     # completion - arrival (closed loop: completion - submission)
     wall_s: float
     n: int
     failed: int
+    submit_lag_ms: List[float]  # submission - arrival (the client's own delay)
+    overlapped: int             # requests whose [start, done] window overlaps another's
 
 
-def _run(srv: Server, sids, reqs, params, arrivals: Optional[np.ndarray], bufs) -> Result:
+def _run(srv: Server, sids, reqs, params, arrivals: Optional[np.ndarray]) -> Result:
     """Submit requests at the given arrival offsets (None: all at once) and wait
-    for all of them.  bufs: one output buffer per request slot in use."""
+    for all of them.  Latency runs from each request's scheduled arrival on the
+    library's clock, so time spent on the client side counts.  Every request
+    gets its own output buffer (from torch's caching allocator), so no request
+    is held back for want of one."""
     n = len(reqs)
     pending = {}
-    lat = []
+    lat, lag, windows = [], [], []
     failed = 0
-    t0 = time.perf_counter()
+    t0 = srv.clock()
     i = 0
-    free = list(range(len(bufs)))
     while i < n or pending:
-        now = time.perf_counter() - t0
-        while i < n and free and (arrivals is None or arrivals[i] <= now):
+        now = srv.clock() - t0
+        while i < n and (arrivals is None or arrivals[i] <= now):
             si, cam = reqs[i]
-            b = free.pop()
-            t = srv.submit(sids[si], cam, params, bufs[b])
-            pending[t] = b
+            buf = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device="cuda")
+            t = srv.submit(sids[si], cam, params, buf)
+            arr = t0 + (arrivals[i] if arrivals is not None else 0.0)
+            pending[t] = (buf, arr)
             i += 1
         for t in list(pending):
-            s, ts, td = srv.poll(t)
+            s, _, _ = srv.poll(t)
             if s >= 2:
+                _, arr = pending.pop(t)
+                ts, tst, td = srv.times(t)
                 if s == 2:
-                    lat.append((td - ts) * 1e3)
+                    lat.append((td - (arr if arrivals is not None else ts)) * 1e3)
+                    lag.append((ts - arr) * 1e3)
+                    windows.append((tst, td))
                 else:
                     failed += 1
-                free.append(pending.pop(t))
                 srv.release(t)
         time.sleep(0.0002)
-    return Result(lat, time.perf_counter() - t0, n, failed)
+    return Result(lat, srv.clock() - t0, n, failed, lag, count_overlapped(windows))
+
+
+def count_overlapped(windows) -> int:
+    """Number of (start, done) windows that overlap at least one other window."""
+    w = sorted(windows)
+    hit = [False] * len(w)
+    end_max, end_idx = -np.inf, -1
+    for i, (a, b) in enumerate(w):
+        if a < end_max:
+            hit[i] = True
+            hit[end_idx] = True
+        if b > end_max:
+            end_max, end_idx = b, i
+    return int(sum(hit))
 
 
 def poisson_benchmark(ctx: Context, n_requests: int = 1000, seed: int = 5, n_scenes: int = 6,
@@ -106,8 +138,8 @@ def poisson_benchmark(ctx: Context, n_requests: int = 1000, seed: int = 5, n_sce
     """Resident BF16 scenes of 256..16384 primitives and 8^3..16^3 payloads;
     requests at 256^2..1920x1080.  Measures closed-loop capacity, then an open
     Poisson stream at each of `loads` x capacity; reports p50/p99 latency
-    (completion - arrival) per load.  The headline p50/p99 are those at the
-    load closest to 0.8."""
+    (completion on the device - scheduled arrival, on the library clock) per
+    load.  The headline p50/p99 are those at the load closest to 0.8."""
     srv = Server(ctx, budget_bytes, slots)
     specs = scenes.serving_scene_specs(seed=4, count=16)
     specs = [specs[i] for i in scene_pick] if scene_pick is not None else specs[:n_scenes]
@@ -118,11 +150,9 @@ def poisson_benchmark(ctx: Context, n_requests: int = 1000, seed: int = 5, n_sce
         del dp
     params = scenes.MarchParams(1.0 / 512, 1e-6)
     reqs = scenes.serving_requests(seed, n_requests, len(sids))
-    maxpix = max(w * h for w, h in scenes.SERVE_RESOLUTIONS)
-    bufs = [torch.empty(maxpix * 4, dtype=torch.float32, device="cuda") for _ in range(16)]
     torch.cuda.synchronize()
-    warm = _run(srv, sids, reqs[: min(8, n_requests)], params, None, bufs)
-    closed = _run(srv, sids, reqs, params, None, bufs)
+    warm = _run(srv, sids, reqs[: min(8, n_requests)], params, None)
+    closed = _run(srv, sids, reqs, params, None)
     capacity = (closed.n - closed.failed) / closed.wall_s
     pixels = sum(cam.width * cam.height for _, cam in reqs)
     per_load = []
@@ -131,14 +161,17 @@ def poisson_benchmark(ctx: Context, n_requests: int = 1000, seed: int = 5, n_sce
         rate = load * capacity
         gaps = np.random.default_rng(seed + 1 + i).exponential(1.0 / rate, size=n_requests)
         arrivals = np.cumsum(gaps) - gaps[0]
-        opened = _run(srv, sids, reqs, params, arrivals, bufs)
+        opened = _run(srv, sids, reqs, params, arrivals)
         failed += opened.failed
         lat = np.array(opened.latency_ms)
+        lag = np.array(opened.submit_lag_ms)
         per_load.append({
             "load": load, "offered_fps": round(rate, 1),
             "achieved_fps": round((opened.n - opened.failed) / opened.wall_s, 1),
             "p50_ms": round(float(np.percentile(lat, 50)), 3) if lat.size else None,
             "p99_ms": round(float(np.percentile(lat, 99)), 3) if lat.size else None,
+            "submit_lag_p99_ms": round(float(np.percentile(lag, 99)), 3) if lag.size else None,
+            "overlapped": opened.overlapped,
         })
     for s in sids:
         srv.release_scene(s)
