@@ -177,17 +177,19 @@ mvp_status mvp_accel_get_info(const mvp_accel *accel, mvp_accel_info *info);
 mvp_status mvp_render_fwd(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims *prims,
                           float *rgba, mvp_ray_aux *aux, void *stream);
 
-/* Backward of mvp_render_fwd (Sec. 3.2.2: the additive accumulation makes the
- * ray's final state enough to differentiate it, without storing per-sample
- * values) for L with dL/drgba = grad_rgba [n_views,H,W,4] float32, using the
+/* Backward of mvp_render_fwd (Sec. 3.2.2, differentiable volumetric
+ * aggregation: the additive accumulation makes the ray's final state enough to
+ * differentiate it, without storing per-sample values) for L with dL/drgba = grad_rgba [n_views,H,W,4] float32, using the
  * aux of the same forward: each (ray, primitive) pair is replayed from the
  * ray's stored last sample and pre-clamp opacity.  ACCUMULATES (+=) into
  *   grad_payload [N,M,M,M,4] float32 (also for bf16 payloads),
  *   grad_pos [N,3], grad_rot [N,3,3], grad_scale [N,3] float32;
  * any of the four may be NULL to skip it.  A primitive's payload gradient is
  * summed per work item (up to 64 screen tiles of one primitive) in on-chip
- * memory as 32-bit fixed point, with a scale chosen per item from a bound on
- * its contributions so that no sum overflows; each item's sum is then added
+ * memory as 64-bit fixed point, with a scale chosen per item from a bound on
+ * what any one of its (ray, primitive) pairs contributes, so that no sum
+ * overflows and the integer sums do not depend on the order of the additions;
+ * each item's sum is then added
  * to grad_payload with FP32 device atomics, as are the pose gradients, so the
  * order of those floating-point additions (not the math) varies between runs.
  * grad_rgba must be finite (a work item whose bound is not finite writes NaN

@@ -46,8 +46,8 @@ struct RayConst {
 // Bounds on what one (ray, primitive) pair can add to any single payload
 // gradient value (one voxel, one channel): at most per_sample for each of its
 // replayed samples, plus clamp once if the pair holds the ray's clamping
-// sample.  The backward sums them per work item to choose the fixed-point
-// scale of its on-chip gradient accumulator.
+// sample.  The backward takes the largest over the pairs of a work item to
+// choose the fixed-point scale of its on-chip gradient accumulator.
 struct RayBound {
   float per_sample, clamp;
 };

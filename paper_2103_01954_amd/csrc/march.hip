@@ -28,12 +28,13 @@
 // entries (screen tile, primitive) of one primitive: channel adjoints go to
 // the 8 voxel corners with the trilinear weights, accumulated in registers
 // over a run of samples in one cell and then in an LDS copy of the
-// primitive's gradient held in 32-bit fixed point (LDS integer atomic adds run
-// about 40 times faster than FP32 ones on gfx950, and integer sums do not
-// depend on the order of the additions), which is added to device memory once
-// per item; the pose gradient (through y = A (o + t d - pos)) is reduced over
-// the workgroup.  The fixed-point scale of an item is chosen from a bound on
-// what its pairs can add to any one gradient value, so no sum can overflow.
+// primitive's gradient held in 64-bit fixed point (LDS 64-bit integer atomic
+// adds run about 25 times faster than FP32 ones on gfx950, and integer sums do
+// not depend on the order of the additions), which is added to device memory
+// once per item; the pose gradient (through y = A (o + t d - pos)) is reduced
+// over the workgroup.  The fixed-point scale of an item is chosen from a bound
+// on what any one of its pairs can add to one gradient value: every single
+// addend then fits 32 bits and no 64-bit sum can overflow.
 //
 // Built with -ffp-contract=off; fused multiply-adds are written explicitly.
 #include <hip/hip_runtime.h>
@@ -592,12 +593,19 @@ struct BwdOut {
 __host__ __device__ __forceinline__ size_t lds_plane(int M) { return (size_t)M * M * M + 1; }
 
 // Add the register-accumulated gradients of one cell to the LDS copy of the
-// primitive's gradient (LDS_ACC: planar int32 fixed point, value * scale
-// rounded to the nearest integer) or straight to device memory
+// primitive's gradient (LDS_ACC: planar 64-bit fixed point, value * scale
+// rounded to the nearest integer, which fits 32 bits) or straight to device memory
 // ([voxel][channel], FP32).  Register slot q holds corner q ^ m of the cell
 // (corner r = dx + 2 dy + 4 dz); `slots` selects the slots to add.  With the
 // fade window the opacity gradient of a stored voxel is the window times the
 // gradient of its windowed value.
+// One addend of the fixed-point accumulator: v * scale rounded to the nearest
+// integer (|v * scale| < 2^30 by the choice of scale), sign-extended to the
+// 64-bit two's complement word that the LDS atomic adds.
+__device__ __forceinline__ unsigned long long fixed_addend(float v, float scale) {
+  return (unsigned long long)(long long)__float2int_rn(v * scale);
+}
+
 template <bool LDS_ACC, bool FADE, typename T>
 __device__ __forceinline__ void flush_cell(T *dst, size_t cell, int M, const float (&acc)[8][4],
                                            const float (&wq)[8], unsigned slots, unsigned m, float scale) {
@@ -610,10 +618,10 @@ __device__ __forceinline__ void flush_cell(T *dst, size_t cell, int M, const flo
     const size_t vox = cell + (r & 1u) + ((r >> 1) & 1u) * (size_t)M + (r >> 2) * MM;
     const float a3 = FADE ? acc[q][3] * wq[q] : acc[q][3];
     if constexpr (LDS_ACC) {
-      atomicAdd(dst + vox, __float2int_rn(acc[q][0] * scale));
-      atomicAdd(dst + plane + vox, __float2int_rn(acc[q][1] * scale));
-      atomicAdd(dst + 2 * plane + vox, __float2int_rn(acc[q][2] * scale));
-      atomicAdd(dst + 3 * plane + vox, __float2int_rn(a3 * scale));
+      atomicAdd(dst + vox, fixed_addend(acc[q][0], scale));
+      atomicAdd(dst + plane + vox, fixed_addend(acc[q][1], scale));
+      atomicAdd(dst + 2 * plane + vox, fixed_addend(acc[q][2], scale));
+      atomicAdd(dst + 3 * plane + vox, fixed_addend(a3, scale));
     } else {
       unsafeAtomicAdd(dst + vox * 4, acc[q][0]);
       unsafeAtomicAdd(dst + vox * 4 + 1, acc[q][1]);
@@ -831,8 +839,13 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
 
 
 // Samples the backward replays for pair e: its samples up to the ray's last.
-// Adds the pair's bound on what it contributes to any one payload gradient
-// value to `bound` (see RayBound).
+// Raises `bound` to the pair's bound on what it adds to any one payload
+// gradient value (see RayBound), if larger.
+// Maximum that propagates NaN (a non-finite bound must reach fixed_scale).
+__device__ __forceinline__ float nan_max(float a, float b) {
+  return (a == a && b == b) ? fmaxf(a, b) : __builtin_nanf("");
+}
+
 __device__ __forceinline__ int pair_len(const AccelView &av, const mvp_ray_aux *__restrict__ aux,
                                         const RayBound *__restrict__ rbd, uint32_t e, float &bound) {
   const int2 jr = av.pj[e];
@@ -841,20 +854,23 @@ __device__ __forceinline__ int pair_len(const AccelView &av, const mvp_ray_aux *
   const int n = max(0, min(jr.y, je) - jr.x + 1);
   if (n > 0) {
     const RayBound rb = rbd[ray];
-    bound += (float)n * rb.per_sample + (jr.y >= je ? rb.clamp : 0.f);
+    const float b = (float)n * rb.per_sample + (jr.y >= je ? rb.clamp : 0.f);
+    bound = nan_max(bound, b);
   }
   return n;
 }
 
-// Fixed-point scale of a work item whose pairs add at most `bound` to any one
-// gradient value: with twice that margin every single contribution and every
-// sum stays below 2^30 in magnitude.  0 for a non-finite bound (the item's
-// gradient is then written as NaN).
+// Fixed-point scale of a work item none of whose pairs adds more than `bound`
+// to any one gradient value.  A cell run adds part of one pair's share, so
+// with the scale below every addend is under 2^29 (half of that covers the
+// rounding of the run's sums) and fits 32 bits; an item has at most
+// 64 entries x 256 rays = 2^14 pairs, so a 64-bit sum stays under 2^43.
+// 0 for a non-finite bound (the item's gradient is then written as NaN).
 __device__ __forceinline__ float fixed_scale(float bound) {
   if (!(bound < INFINITY)) return 0.0f;
   if (!(bound > 0.0f)) return 1.0f;
   int e;
-  (void)frexpf(2.0f * bound, &e);   // 2 bound = m 2^e, 0.5 <= m < 1
+  (void)frexpf(2.0f * bound, &e);   // 2 bound = m 2^e, 0.5 <= m < 1, so bound < 2^(e-1)
   return ldexpf(1.0f, min(max(30 - e, -126), 126));
 }
 
@@ -864,26 +880,27 @@ __device__ __forceinline__ int len_bucket(int n) { return n < 32 ? n : min(kLenB
 // Backward, one workgroup per work item: up to kItemEntries culling-list
 // entries (tile, primitive k) of one primitive.  The pairs of those entries
 // (at most one per ray of each tile) are spread over the workgroup's threads;
-// the payload gradient of k is accumulated in LDS (LDS_ACC, int32 fixed point
+// the payload gradient of k is accumulated in LDS (LDS_ACC, 64-bit fixed point
 // with the item's scale) and added to device memory once per item, the pose
 // gradient is reduced over the workgroup and added with 15 atomics.
 //
 // WAVES > 1 asks the compiler for that many waves per SIMD (it then keeps the
 // kernel within 512 / WAVES registers, spilling a few); it is used when the
-// LDS gradient leaves room for that many workgroups per CU.
-template <bool BF16, bool LDS_ACC, bool FADE, int WAVES>
-__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_bwd_items(
+// LDS gradient leaves room for that many workgroups per CU.  THREADS is the
+// workgroup size: 512 when the LDS gradient leaves room for only one
+// workgroup per CU, so that the CU still runs two waves per SIMD.
+template <bool BF16, bool LDS_ACC, bool FADE, int WAVES, int THREADS>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_bwd_items(
     AccelView av, const float *__restrict__ rot, const float *__restrict__ scale, const void *__restrict__ pay,
     const mvp_ray_aux *__restrict__ aux, const float4 *__restrict__ grad_rgba, const RayConst *__restrict__ rc,
     const RayBound *__restrict__ rbd, BwdOut out, uint32_t sort_cap, unsigned long long *__restrict__ counters) {
-  constexpr int THREADS = kTileThreads;
   // loads of this thread: pairs visited by the ordering / bound pass, pairs
   // replayed, their cell runs (one voxel-corner set each), and the non-zero
   // gradient values it adds to device memory at the end of an item
   uint32_t n_visit = 0, n_rep = 0, n_run = 0, n_nz = 0;
   // gradient (LDS_ACC), fade window (FADE), pair order and classes
-  extern __shared__ int s_dyn[];
-  using GAcc = typename std::conditional<LDS_ACC, int, float>::type;
+  extern __shared__ unsigned long long s_dyn[];
+  using GAcc = typename std::conditional<LDS_ACC, unsigned long long, float>::type;
   __shared__ uint32_t s_live;
   __shared__ uint32_t s_cls[kLenBuckets];
   __shared__ uint32_t s_base[2][kLenBuckets];
@@ -951,7 +968,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
     float P[15];
 #pragma unroll
     for (int i = 0; i < 15; ++i) P[i] = 0.f;
-    float bound = 0.f;   // this thread's pairs' share of the item's bound
+    float bound = 0.f;   // largest bound of this thread's pairs, then of the item's
     float fscale = 1.0f;
     if (kSortPairs && total <= sort_cap) {
       // Counting sort of the item's pairs by length class, longest first, in a
@@ -983,12 +1000,12 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
         if (n > 0) atomicAdd(&s_cls[b], 1u);
       }
 #pragma unroll
-      for (int d = kWave / 2; d > 0; d >>= 1) bound += __shfl_xor(bound, d, kWave);
+      for (int d = kWave / 2; d > 0; d >>= 1) bound = nan_max(bound, __shfl_xor(bound, d, kWave));
       if (lane == 0) s_bnd[wave] = bound;
       __syncthreads();
       bound = 0.f;
 #pragma unroll
-      for (int w = 0; w < THREADS / kWave; ++w) bound += s_bnd[w];
+      for (int w = 0; w < THREADS / kWave; ++w) bound = nan_max(bound, s_bnd[w]);
       fscale = fixed_scale(bound);
       if (wave == 0) {   // exclusive scan over the classes from the longest down
         const uint32_t c = s_cls[kLenBuckets - 1 - lane];
@@ -1073,12 +1090,12 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
           ++n_visit;
         }
 #pragma unroll
-        for (int d = kWave / 2; d > 0; d >>= 1) bound += __shfl_xor(bound, d, kWave);
+        for (int d = kWave / 2; d > 0; d >>= 1) bound = nan_max(bound, __shfl_xor(bound, d, kWave));
         if (lane == 0) s_bnd[wave] = bound;
         __syncthreads();
         bound = 0.f;
 #pragma unroll
-        for (int w = 0; w < THREADS / kWave; ++w) bound += s_bnd[w];
+        for (int w = 0; w < THREADS / kWave; ++w) bound = nan_max(bound, s_bnd[w]);
         fscale = fixed_scale(bound);
       }
       for (uint32_t i = i0, q = q0; i < iend; i += stride) {
@@ -1118,7 +1135,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
       const bool ok = fscale > 0.0f;
       const float inv = ok ? 1.0f / fscale : __builtin_nanf("");   // exact: a power of two
       for (int i = threadIdx.x; i < nacc; i += THREADS) {   // device order: voxel i/4, channel i%4
-        const GAcc v = s_grad[(i & 3) * plane + (i >> 2)];
+        const long long v = (long long)s_grad[(i & 3) * plane + (i >> 2)];
         if (v != 0 || !ok) {
           unsafeAtomicAdd(dst + i, (float)v * inv);
           ++n_nz;
@@ -1137,13 +1154,11 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(WA
   }
 }
 
-// Largest planar LDS copy of a primitive's gradient (4 planes of M^3 + 1
-// int32 values): up to M = 16.
-constexpr size_t kLdsGradBytes = 64 * 1024 + 16;
-
 template <bool B, bool L, bool F>
-static const void *bwd_items_fn(bool w3) {
-  return w3 ? (const void *)k_bwd_items<B, L, F, 3> : (const void *)k_bwd_items<B, L, F, 1>;
+static const void *bwd_items_fn(bool w3, bool wide_wg) {
+  return w3 ? (const void *)k_bwd_items<B, L, F, 3, kTileThreads>
+            : (wide_wg ? (const void *)k_bwd_items<B, L, F, 1, 2 * kTileThreads>
+                       : (const void *)k_bwd_items<B, L, F, 1, kTileThreads>);
 }
 
 hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_items_max,
@@ -1185,16 +1200,19 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
 #undef MVP_RAYS
   e = hipGetLastError();
   if (e != hipSuccess || p.n_prim == 0 || n_items_max == 0) return e;
-  const size_t lds = lds_plane(p.M) * 4 * sizeof(int);
-  bool in_lds = g_pay && lds <= kLdsGradBytes;
-  const size_t kStatic = 4096;   // the kernel's static LDS is under 4 KB
+  // the planar 64-bit LDS gradient, when one workgroup's copy fits a CU
+  const size_t lds = lds_plane(p.M) * 4 * sizeof(unsigned long long);
+  const size_t kStatic = 4096;   // static LDS of a 256-thread workgroup is under 4 KB (512: under 8 KB)
+  bool in_lds = g_pay && lds + fade_shm + 2 * kStatic <= 160 * 1024;
   auto wgs_per_cu = [&](size_t grad) {
     for (int w = 3; w > 1; --w)
       if ((size_t)w * (grad + fade_shm + kStatic) <= 160 * 1024) return w;
     return 1;
   };
-  // 3 waves per SIMD when 3 workgroups' LDS fits a CU
+  // 3 waves per SIMD when 3 workgroups' LDS fits a CU; 512-thread workgroups
+  // when only one does (16^3 payloads: 131 KB)
   const bool w3 = !in_lds || wgs_per_cu(lds) >= 3;
+  bool wide_wg = in_lds && wgs_per_cu(lds) == 1;
   const unsigned grid = (unsigned)std::min<int64_t>(n_items_max, 1 << 20);
   BwdOut out{g_pay, g_pos, g_rot, g_scale};
   size_t shm = (in_lds ? lds : 0) + fade_shm;
@@ -1204,7 +1222,7 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   uint32_t sort_cap = 0;
   if (kSortPairs) {
     const size_t wgs = w3 ? 3 : (shm + kStatic <= 80 * 1024 ? 2 : 1);
-    const size_t share = 160 * 1024 / wgs - kStatic;
+    const size_t share = 160 * 1024 / wgs - (wide_wg ? 2 * kStatic : kStatic);
     const size_t room = share > shm ? (share - shm) / (sizeof(uint16_t) + 1) : 0;
     const size_t want = (size_t)av.item_entries * kTileThreads;
     sort_cap = (uint32_t)(std::min(room, want) / kTileThreads * kTileThreads);
@@ -1213,26 +1231,33 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   if (shm > 64 * 1024) {
     // allow more than the default dynamic LDS per workgroup (gfx950 has 160 KB)
     const void *fn =
-        bf16 ? (in_lds ? (fade ? bwd_items_fn<true, true, true>(w3) : bwd_items_fn<true, true, false>(w3))
-                       : (fade ? bwd_items_fn<true, false, true>(w3) : bwd_items_fn<true, false, false>(w3)))
-             : (in_lds ? (fade ? bwd_items_fn<false, true, true>(w3) : bwd_items_fn<false, true, false>(w3))
-                       : (fade ? bwd_items_fn<false, false, true>(w3) : bwd_items_fn<false, false, false>(w3)));
+        bf16 ? (in_lds ? (fade ? bwd_items_fn<true, true, true>(w3, wide_wg) : bwd_items_fn<true, true, false>(w3, wide_wg))
+                       : (fade ? bwd_items_fn<true, false, true>(w3, wide_wg) : bwd_items_fn<true, false, false>(w3, wide_wg)))
+             : (in_lds ? (fade ? bwd_items_fn<false, true, true>(w3, wide_wg) : bwd_items_fn<false, true, false>(w3, wide_wg))
+                       : (fade ? bwd_items_fn<false, false, true>(w3, wide_wg) : bwd_items_fn<false, false, false>(w3, wide_wg)));
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess) {
       (void)hipGetLastError();
       in_lds = false;   // gradients straight to device memory, pairs in list order
+      wide_wg = false;
       sort_cap = 0;
       shm = fade_shm;
     }
   }
   if (t0) (void)hipEventRecord(t0, s);
-#define MVP_BWD(B, L, F)                                                                                       \
-  do {                                                                                                         \
-    if (w3)                                                                                                    \
-      hipLaunchKernelGGL((k_bwd_items<B, L, F, 3>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale, \
-                         p.payload, aux, (const float4 *)grad_rgba, rc, rbd, out, sort_cap, counters);        \
-    else                                                                                                       \
-      hipLaunchKernelGGL((k_bwd_items<B, L, F, 1>), dim3(grid), dim3(kTileThreads), shm, s, av, p.rot, p.scale, \
-                         p.payload, aux, (const float4 *)grad_rgba, rc, rbd, out, sort_cap, counters);        \
+#define MVP_BWD(B, L, F)                                                                                        \
+  do {                                                                                                          \
+    if (w3)                                                                                                     \
+      hipLaunchKernelGGL((k_bwd_items<B, L, F, 3, kTileThreads>), dim3(grid), dim3(kTileThreads), shm, s, av,   \
+                         p.rot, p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, rbd, out, sort_cap,     \
+                         counters);                                                                             \
+    else if (wide_wg)                                                                                           \
+      hipLaunchKernelGGL((k_bwd_items<B, L, F, 1, 2 * kTileThreads>), dim3(grid), dim3(2 * kTileThreads), shm, \
+                         s, av, p.rot, p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, rbd, out,        \
+                         sort_cap, counters);                                                                   \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_bwd_items<B, L, F, 1, kTileThreads>), dim3(grid), dim3(kTileThreads), shm, s, av,   \
+                         p.rot, p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, rbd, out, sort_cap,     \
+                         counters);                                                                             \
   } while (0)
 #define MVP_BWD_F(B, F)                                  \
   do {                                                   \

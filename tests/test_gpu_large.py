@@ -50,5 +50,12 @@ def test_large_forward_and_backward_sampled(mvp_ctx, c4):
     grads = acc.render_bwd(dp, aux, torch.from_numpy(up.astype(np.float32)).cuda())
     torch.cuda.synchronize()
     got = {k: grads[k].cpu().numpy().astype(np.float64).reshape(ref[k].shape) for k in GROUPS}
-    check_grads(got, ref, 1e-4, GROUPS)
+    # Per-primitive floor 0.1 (allowance 1e-5 of the largest primitive's gradient
+    # norm): 256 random rays touch thousands of primitives here, many only
+    # through a few samples near a cell face.  Those gradients are proportional
+    # to small trilinear weights, whose rounding from the FP32 sample position is
+    # absolute rather than relative (one primitive touching a single cell shows
+    # 9e-4 relative, the same with FP32 device atomics as with the fixed-point
+    # accumulator).
+    check_grads(got, ref, 1e-4, GROUPS, floor=0.1)
     acc.destroy()
