@@ -200,6 +200,27 @@ mvp_status mvp_render_bwd(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims 
                           float *grad_payload, float *grad_pos, float *grad_rot,
                           float *grad_scale, void *stream);
 
+/* Largest number of rays (pixels of all views, or entries of a ray subset) of
+ * one mvp_render_bwd_noalloc call: one 1024x1024 view. */
+#define MVP_NOALLOC_MAX_RAYS 1048576
+
+/* mvp_render_bwd for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors as mvp_render_bwd, but the
+ * 24 bytes per ray of scratch come from a fixed library-owned device array
+ * (24 MiB on every device the library runs on, held until the process ends)
+ * instead of the context's memory cache, so the call allocates nothing.
+ * A structure with more than MVP_NOALLOC_MAX_RAYS rays fails with
+ * MVP_ERR_INVALID and enqueues nothing.  All calls on one device share that
+ * array: calls that may overlap on one device (different streams or threads,
+ * or different contexts) race and must be serialised by the caller; calls on
+ * one stream are ordered and safe.  Nothing in the array needs to survive a
+ * call, and the call clears what it needs cleared with kernels (no memset). */
+mvp_status mvp_render_bwd_noalloc(mvp_ctx *ctx, const mvp_accel *accel, const mvp_prims *prims,
+                                  const mvp_ray_aux *aux, const float *grad_rgba,
+                                  float *grad_payload, float *grad_pos, float *grad_rot,
+                                  float *grad_scale, void *stream);
+
 /* The same forward composited over a background (the alpha compositing of
  * Sec. 3.1.4 with the premultiplied colour): rgba = (I + (1 - A) B, A) with
  * background B [rays,3] float32 (rays ordered like rgba). */

@@ -26,6 +26,7 @@ class mvp_prims(C.Structure):
 
 MVP_COMBINE_SUM, MVP_COMBINE_SEQUENTIAL = 0, 1
 MVP_KERNEL_FWD_MARCH, MVP_KERNEL_BWD_MARCH = 0, 1
+MVP_NOALLOC_MAX_RAYS = 1048576
 
 
 class mvp_camera(C.Structure):
@@ -68,6 +69,7 @@ _SIGS = {
     "mvp_accel_get_info": ([P, C.POINTER(mvp_accel_info)], C.c_int),
     "mvp_render_fwd": ([P, P, C.POINTER(mvp_prims), P, P, P], C.c_int),
     "mvp_render_bwd": ([P, P, C.POINTER(mvp_prims), P, P, P, P, P, P, P], C.c_int),
+    "mvp_render_bwd_noalloc": ([P, P, C.POINTER(mvp_prims), P, P, P, P, P, P, P], C.c_int),
     "mvp_render_fwd_bg": ([P, P, C.POINTER(mvp_prims), P, P, P, P], C.c_int),
     "mvp_render_bwd_bg": ([P, P, C.POINTER(mvp_prims), P, P, P, P, P, P, P, P, P, P], C.c_int),
     "mvp_accel_counts": ([P, P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), P], C.c_int),

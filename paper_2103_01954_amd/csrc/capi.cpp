@@ -410,6 +410,43 @@ mvp_status destroy_accel(mvp_ctx *ctx, mvp_accel *a, hipStream_t s) {
   return st;
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free backward: per-ray scratch in a fixed device array
+// ---------------------------------------------------------------------------
+
+// Scratch of mvp_render_bwd_noalloc: room for the per-ray constants and bounds
+// of MVP_NOALLOC_MAX_RAYS rays (24 MiB).  Every device the library runs on
+// holds its own copy until the process ends.  In host code `scratch` names a
+// host-side stand-in, never the device memory: kernels and copies get the
+// address that hipGetSymbolAddress returns for the device, kept in
+// g_scratch[device] by resolve_scratch.
+static __device__ __align__(256) unsigned char scratch[bwd_scratch_bytes(MVP_NOALLOC_MAX_RAYS)];
+constexpr int kMaxDevices = 64;
+static void *g_scratch[kMaxDevices];
+static hipError_t g_scratch_err[kMaxDevices];
+static std::once_flag g_scratch_once[kMaxDevices];
+
+// Resolve this device's copy of `scratch`, once per device; the device must be
+// current.  Called by mvp_create.
+static mvp_status resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device %d beyond the %d devices the library supports", device, kMaxDevices);
+    return MVP_ERR_INVALID;
+  }
+  std::call_once(g_scratch_once[device], [device] {
+    void *ptr = nullptr;
+    g_scratch_err[device] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (g_scratch_err[device] == hipSuccess) g_scratch[device] = ptr;
+    else (void)hipGetLastError();
+  });
+  if (!g_scratch[device]) {
+    set_error("hipGetSymbolAddress of the backward scratch array failed on device %d: %s", device,
+              hipGetErrorString(g_scratch_err[device]));
+    return MVP_ERR_DEVICE;
+  }
+  return MVP_OK;
+}
+
 static mvp_status check_render(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *p) {
   if (!ctx || !a || a->ctx != ctx) { set_error("bad context or accel handle"); return MVP_ERR_INVALID; }
   MVP_CHECK(check_prims(p, true));
@@ -437,6 +474,7 @@ mvp_status mvp_create(int device, mvp_ctx **out) {
   MVP_HIP(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) { set_error("device %d out of range (%d devices)", device, n); return MVP_ERR_INVALID; }
   MVP_HIP(hipSetDevice(device));
+  MVP_CHECK(resolve_scratch(device));
   mvp_ctx *c = new (std::nothrow) mvp_ctx(device);
   if (!c) { set_error("host allocation failed"); return MVP_ERR_OOM; }
   *out = c;
@@ -585,6 +623,26 @@ mvp_status mvp_render_bwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *pri
                           float *grad_scale, void *stream) {
   return render_bwd(ctx, a, prims, nullptr, nullptr, aux, grad_rgba, grad_payload, grad_pos, grad_rot, grad_scale,
                     nullptr, (hipStream_t)stream);
+}
+
+mvp_status mvp_render_bwd_noalloc(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims,
+                                  const mvp_ray_aux *aux, const float *grad_rgba, float *grad_payload,
+                                  float *grad_pos, float *grad_rot, float *grad_scale, void *stream) {
+  MVP_CHECK(check_render(ctx, a, prims));
+  if ((!aux || !grad_rgba) && a->n_slots > 0) { set_error("aux and grad_rgba are required"); return MVP_ERR_INVALID; }
+  if (a->n_rays() > (size_t)MVP_NOALLOC_MAX_RAYS) {
+    set_error("%zu rays exceed the %d of the allocation-free backward (use mvp_render_bwd)", a->n_rays(),
+              MVP_NOALLOC_MAX_RAYS);
+    return MVP_ERR_INVALID;
+  }
+  void *ptr = (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_scratch[ctx->device] : nullptr;
+  if (!ptr) { set_error("the backward scratch array of device %d was not resolved", ctx->device); return MVP_ERR_DEVICE; }
+  MVP_HIP(hipSetDevice(ctx->device));
+  const auto ev = timer_slot(ctx, MVP_KERNEL_BWD_MARCH);
+  MVP_HIP(launch_march_bwd(a->view(prims->M), *prims, a->n_items_max, aux, grad_rgba, nullptr, nullptr, ptr,
+                           grad_payload, grad_pos, grad_rot, grad_scale, nullptr, a->counters, (hipStream_t)stream,
+                           ev.first, ev.second));
+  return MVP_OK;
 }
 
 mvp_status mvp_render_bwd_bg(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *prims, const float *background,
