@@ -127,22 +127,23 @@ def cpu_baseline(size, views, n_rows):
 
 def fwd_bytes(lc, dtype, rays, aux=True):
     """Bytes k_march_fwd loads and stores per launch: voxel-corner sets (8
-    corners), pair intervals (8 B) and pair local rays (pa + pb, 32 B) as
-    counted by the kernel, plus per ray its two list offsets (16 B) and its
-    outputs (rgba 16 B, aux 8 B)."""
-    return (lc["fwd_cells"] * 8 * VOX[dtype] + lc["fwd_pair_intervals"] * 8 + lc["fwd_pair_rays"] * 32
+    corners), pair records (16 B) and culling-entry frames read from device
+    memory (52 B: the tile's frames staged once per tile, or per pair for long
+    lists) as counted by the kernel, plus per ray its segment and count (16 B)
+    and its outputs (rgba 16 B, aux 8 B)."""
+    return (lc["fwd_cells"] * 8 * VOX[dtype] + lc["fwd_pair_intervals"] * 16 + lc["fwd_pair_rays"] * 52
             + rays * (16 + 16 + (8 if aux else 0)))
 
 
 def bwd_bytes(lc, dtype, pose=True):
     """Bytes k_bwd_items loads and stores per launch: per pair visited by the
-    ordering pass 28 B (list slot 4, interval 8, ray index 4, the ray's last
-    sample 4, its bounds 8); per pair replayed 84 B (list slot 4, pa 16, pb 16,
-    pj 8, aux 8, upstream gradient 16, ray constants 16) plus 144 B for the pose
-    chain (camera 48, world-to-local rows 48, rotation 36, scale 12); per cell
-    run one voxel-corner set (8 corners); per non-zero gradient value added to
-    device memory 4 B."""
-    return (lc["bwd_pairs_visited"] * 28 + lc["bwd_pairs_replayed"] * (84 + (144 if pose else 0))
+    ordering pass 24 B (entry record 8, the ray's last sample 8, its bounds 8);
+    per pair replayed 104 B (entry record 8, entry frame 48, aux 8, upstream
+    gradient 16, ray constants 16, camera 8 of its origin and matrix, cached)
+    plus 80 B for the pose chain (position 16, rotation 36, scale 12, camera
+    16); per cell run one voxel-corner set (8 corners); per non-zero gradient
+    value added to device memory 4 B."""
+    return (lc["bwd_pairs_visited"] * 24 + lc["bwd_pairs_replayed"] * (104 + (80 if pose else 0))
             + lc["bwd_cell_runs"] * 8 * VOX[dtype] + lc["bwd_grad_flush"] * 4)
 
 

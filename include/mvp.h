@@ -146,7 +146,7 @@ const char *mvp_version(void);
  * the fixed-step sample interval inside each (the ray-specific lists and
  * domain of integration of Sec. 3.2.1).  cams is a HOST array of n_views.
  * Reads prims->pos/rot/scale; the payload is not read.  BLOCKS until the list
- * sizes are known (two stream synchronisations).  *out must be released with
+ * sizes are known (one stream synchronisation).  *out must be released with
  * mvp_accel_destroy. */
 mvp_status mvp_build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams,
                            int32_t n_views, const mvp_march_params *params,
@@ -166,6 +166,8 @@ mvp_status mvp_build_accel_rays(mvp_ctx *ctx, const mvp_prims *prims, const mvp_
 /* Release an acceleration structure.  Its memory is recycled only after the
  * work already enqueued on `stream` has finished. */
 mvp_status mvp_accel_destroy(mvp_ctx *ctx, mvp_accel *accel, void *stream);
+/* Sizes of a structure.  The first call BLOCKS until the structure's build
+ * has finished on the device (the pair count is counted there). */
 mvp_status mvp_accel_get_info(const mvp_accel *accel, mvp_accel_info *info);
 
 /* Forward march (Sec. 3.2.2).  prims must be the primitives the structure was
@@ -245,8 +247,9 @@ mvp_status mvp_accel_counts(mvp_ctx *ctx, const mvp_accel *accel, uint64_t *ray_
 /* Load counts of the most recent forward and backward on this structure
  * (BLOCKS on `stream`), written to the HOST array out[9]:
  *   [0] ray-samples, [1] prim-samples (as mvp_accel_counts);
- *   forward: [2] voxel-corner sets loaded (8 corners each), [3] pair-interval
- *   loads (8 B each), [4] pair local-ray loads (32 B each);
+ *   forward: [2] voxel-corner sets loaded (8 corners each), [3] pair-record
+ *   loads (16 B each), [4] culling-entry frames read from device memory
+ *   (52 B each; a tile's frames are staged once per tile when they fit);
  *   backward: [5] pairs visited by its ordering pass, [6] pairs replayed,
  *   [7] cell runs (one voxel-corner set loaded each), [8] non-zero payload
  *   gradient values added to grad_payload.

@@ -283,35 +283,42 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   struct Guard {
     mvp_accel *a;
     bool keep = false;
-    ~Guard() { if (!keep) delete a; }
+    ~Guard() {
+      if (keep) return;
+      if (a->built) (void)hipEventDestroy(a->built);
+      delete a;
+    }
   } guard{a};
 
   MVP_HIP(hipSetDevice(ctx->device));
   Blocks keep{ctx, s}, temp{ctx, s};
   int4 *rect = nullptr;
-  uint32_t *tile_cnt = nullptr, *ray_cnt = nullptr, *entry_cnt = nullptr;
-  uint8_t *scratch = nullptr, *scratch2 = nullptr;
-  const size_t sb = scan_scratch_bytes(std::max<size_t>(std::max<size_t>(ntile, R), (size_t)N));
+  uint32_t *tile_cnt = nullptr, *cap = nullptr, *rcnt = nullptr, *depth = nullptr;
+  uint8_t *scratch = nullptr;
+  const size_t sb = scan_scratch_bytes(std::max<size_t>(ntile, (size_t)N));
   if (admit) {
-    const size_t base = n_views * sizeof(DevCam) + 3 * (size_t)N * 16 + (ntile + 1) * 8 + (R + 1) * 8 + 16 +
-                        (size_t)n_views * N * 16 + ntile * 4 + R * 4 + sb + 9 * 256 +
+    const size_t base = n_views * sizeof(DevCam) + 3 * (size_t)N * 16 + 2 * (ntile + 1) * 8 + R * 16 + 16 +
+                        kNumCounters * 8 + (size_t)n_views * N * 20 + 2 * ntile * 4 + sb + 10 * 256 +
                         (rays ? R * 12 + ntile * 12 + 3 * 256 : 0);
     MVP_CHECK(admit->fn(admit->user, base));
   }
   MVP_CHECK(keep.get(&a->cams, n_views));
   MVP_CHECK(keep.get(&a->xf, 3 * (size_t)N));
   MVP_CHECK(keep.get(&a->tile_off, ntile + 1));
-  MVP_CHECK(keep.get(&a->ray_off, R + 1));
+  MVP_CHECK(keep.get(&a->pair_base, ntile + 1));
+  MVP_CHECK(keep.get(&a->ray_seg, R ? R : 1));
+  MVP_CHECK(keep.get(&a->ray_nj, R ? R : 1));
   MVP_CHECK(keep.get(&a->counters, kNumCounters));
   MVP_CHECK(temp.get(&rect, (size_t)n_views * N));
+  MVP_CHECK(temp.get(&depth, (size_t)n_views * N));
   MVP_CHECK(temp.get(&tile_cnt, ntile));
-  MVP_CHECK(temp.get(&ray_cnt, R));
+  MVP_CHECK(temp.get(&cap, ntile));
   MVP_CHECK(temp.get(&scratch, sb));
   MVP_HIP(hipMemcpyAsync(a->cams, a->cams_host.data(), n_views * sizeof(DevCam), hipMemcpyHostToDevice, s));
+  MVP_HIP(launch_zero_u64((uint64_t *)a->counters, kNumCounters, s));
   uint32_t *flag = nullptr;
   if (rays) {
     // ray subset: a private copy of the pixel ids, binned into screen tiles
-    uint32_t *rcnt = nullptr;
     MVP_CHECK(keep.get(&a->ray_pix, R ? R : 1));
     MVP_CHECK(keep.get(&a->tile_ray_off, ntile + 1));
     MVP_CHECK(keep.get(&a->tile_rays, R ? R : 1));
@@ -323,77 +330,82 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
     MVP_HIP(launch_zero_u32(flag, 1, s));
     MVP_HIP(launch_ray_bin(rv, rcnt, flag, s));
     MVP_HIP(launch_scan_u32_u64(rcnt, a->tile_ray_off, ntile, scratch, s));
-    MVP_HIP(launch_zero_u32(rcnt, ntile, s));
-    MVP_HIP(launch_ray_fill(rv, rcnt, a->tile_rays, s));
-    MVP_HIP(launch_segment_sort(a->tile_ray_off, a->tile_rays, (int64_t)ntile, s));
+    // rcnt keeps the per-tile ray counts (for the pair capacities); the fill
+    // takes its own cursor
+    uint32_t *cursor = nullptr;
+    MVP_CHECK(temp.get(&cursor, ntile));
+    MVP_HIP(launch_zero_u32(cursor, ntile, s));
+    MVP_HIP(launch_ray_fill(rv, cursor, a->tile_rays, s));
+    MVP_HIP(launch_segment_sort(a->tile_ray_off, a->tile_rays, (int64_t)ntile, nullptr, 0, 1, s));
   }
   AccelView av = a->view(2);
 
-  // culling lists: rectangles, tile counts, offsets, fill, sort by primitive id
+  // culling lists: rectangles, tile counts, offsets; pair capacities; one
+  // stream synchronisation for the sizes
   MVP_HIP(launch_zero_u32(tile_cnt, ntile, s));
-  MVP_HIP(launch_prep(*prims, av, a->xf, rect, tile_cnt, s));
+  MVP_HIP(launch_prep(*prims, av, a->xf, rect, depth, tile_cnt, s));
   MVP_HIP(launch_scan_u32_u64(tile_cnt, a->tile_off, ntile, scratch, s));
-  uint64_t n_tile_pairs = 0;
+  MVP_HIP(launch_tile_capacity(tile_cnt, rcnt, ntile, cap, s));
+  MVP_HIP(launch_scan_u32_u64(cap, a->pair_base, ntile, scratch, s));
+  uint64_t sizes[2] = {0, 0};
   uint32_t flag_h = 0;
   if (flag) MVP_HIP(hipMemcpyAsync(&flag_h, flag, sizeof flag_h, hipMemcpyDeviceToHost, s));
-  MVP_CHECK(read_u64(a->tile_off + ntile, &n_tile_pairs, s));
+  MVP_HIP(hipMemcpyAsync(&sizes[0], a->tile_off + ntile, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  MVP_HIP(hipMemcpyAsync(&sizes[1], a->pair_base + ntile, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  MVP_HIP(hipStreamSynchronize(s));
+  const uint64_t n_tile_pairs = sizes[0], capacity = sizes[1];
   if (flag_h & 1u) { set_error("a ray pixel id is outside [0, n_views*height*width)"); return MVP_ERR_INVALID; }
   if (flag_h & 2u) { set_error("more than 256 rays in one 16x16 tile (repeated pixel ids)"); return MVP_ERR_INVALID; }
+  if (capacity >= (uint64_t)1 << 32) {
+    set_error("%llu ray/primitive pair slots exceed 2^32 (%llu culling-list entries)", (unsigned long long)capacity,
+              (unsigned long long)n_tile_pairs);
+    return MVP_ERR_INVALID;
+  }
   const size_t ntp = n_tile_pairs ? n_tile_pairs : 1;
-  const size_t sb2 = scan_scratch_bytes(n_tile_pairs);
-  if (admit) MVP_CHECK(admit->fn(admit->user, ntp * 20 + 8 + sb2 + (size_t)N * 20 + 24 + 8 * 256));
+  const size_t npc = capacity ? capacity : 1;
+  if (admit)
+    MVP_CHECK(admit->fn(admit->user, ntp * (4 + 4 + 48 + 8 + 16 + 4) + (size_t)N * 20 + 24 + npc * 24 + 8 * 256));
   MVP_CHECK(keep.get(&a->tile_list, ntp));
-  MVP_CHECK(keep.get(&a->entry_off, ntp + 1));
   MVP_CHECK(keep.get(&a->prim_entries, ntp));
   MVP_CHECK(keep.get(&a->prim_entry_off, (size_t)N + 1));
   MVP_CHECK(keep.get(&a->item_off, (size_t)N + 1));
+  MVP_CHECK(keep.get(&a->ef, 3 * ntp));
+  MVP_CHECK(keep.get(&a->ent_base, ntp));
+  MVP_CHECK(keep.get(&a->ent_n, 4 * ntp));
+  MVP_CHECK(keep.get(&a->ent_tile, ntp));
+  MVP_CHECK(keep.get(&a->pr, npc));
+  MVP_CHECK(keep.get(&a->ent_rec, npc));
   uint32_t *prim_cnt = nullptr;
   MVP_CHECK(temp.get(&prim_cnt, (size_t)N + 1));
-  MVP_CHECK(temp.get(&entry_cnt, ntp));
-  MVP_CHECK(temp.get(&scratch2, sb2));
   av = a->view(2);
   MVP_HIP(launch_zero_u32(tile_cnt, ntile, s));
   MVP_HIP(launch_tile_fill(av, rect, tile_cnt, a->tile_list, s));
-  MVP_HIP(launch_segment_sort(a->tile_off, a->tile_list, (int64_t)ntile, s));
+  MVP_HIP(launch_segment_sort(a->tile_off, a->tile_list, (int64_t)ntile, depth, N, tx * ty, s));
   // transposed lists (primitive -> its entries) and backward work items
   MVP_HIP(launch_zero_u32(prim_cnt, (size_t)N, s));
   MVP_HIP(launch_prim_entry_count(a->tile_list, n_tile_pairs, prim_cnt, s));
   MVP_HIP(launch_scan_u32_u64(prim_cnt, a->prim_entry_off, (size_t)N, scratch, s));
-  MVP_HIP(launch_zero_u32(prim_cnt, (size_t)N, s));
-  MVP_HIP(launch_prim_entry_fill(a->tile_list, n_tile_pairs, a->prim_entry_off, prim_cnt, a->prim_entries, s));
-  MVP_HIP(launch_segment_sort(a->prim_entry_off, a->prim_entries, (int64_t)N, s));
+  MVP_HIP(launch_prim_entry_place(av, rect, n_tile_pairs, a->prim_entry_off, a->prim_entries, s));
   a->item_entries = backward_item_entries(prims->M);
   MVP_HIP(launch_item_count(a->prim_entry_off, N, a->item_entries, prim_cnt, s));
   MVP_HIP(launch_scan_u32_u64(prim_cnt, a->item_off, (size_t)N, scratch, s));
   a->n_items_max = (int64_t)(n_tile_pairs / a->item_entries) + N;
 
-  // per-ray pair counts and per-entry counts, offsets
-  MVP_HIP(launch_hit_count(av, 0, ray_cnt, entry_cnt, s));
-  MVP_HIP(launch_scan_u32_u64(ray_cnt, a->ray_off, R, scratch, s));
-  MVP_HIP(launch_scan_u32_u64(entry_cnt, a->entry_off, n_tile_pairs, scratch2, s));
-  uint64_t n_pairs = 0;
-  MVP_CHECK(read_u64(a->ray_off + R, &n_pairs, s));
-  if (n_pairs >= (uint64_t)1 << 32) { set_error("%llu ray/primitive pairs exceed 2^32", (unsigned long long)n_pairs); return MVP_ERR_INVALID; }
-  const size_t np = n_pairs ? n_pairs : 1;
-  if (admit) MVP_CHECK(admit->fn(admit->user, np * 52 + 8 * 256));
-  int32_t *tkey = nullptr;
-  uint32_t *trank = nullptr;
-  MVP_CHECK(keep.get(&a->pa, np));
-  MVP_CHECK(keep.get(&a->pb, np));
-  MVP_CHECK(keep.get(&a->pj, np));
-  MVP_CHECK(keep.get(&a->entry_pairs, np));
-  MVP_CHECK(temp.get(&tkey, np));
-  MVP_CHECK(temp.get(&trank, np));
-  av = a->view(2);
-  MVP_HIP(launch_hit_emit(av, 0, tkey, trank, a->pa, a->pb, a->pj, a->entry_pairs, nullptr, s));
+  // every ray's pairs, the entry frames and the per-entry pair lists
+  MVP_HIP(launch_pairs(av, a->ef, a->pr, a->ray_seg, a->ray_nj, a->ent_base, a->ent_n, a->ent_tile, a->ent_rec,
+                       a->counters + kCntPairs, s));
+  MVP_HIP(hipEventCreateWithFlags(&a->built, hipEventDisableTiming));
+  MVP_HIP(hipEventRecord(a->built, s));
 
   a->n_tile_pairs = (int64_t)n_tile_pairs;
-  a->n_ray_pairs = (int64_t)n_pairs;
-  a->bytes = (int64_t)(n_views * sizeof(DevCam) + 3 * (size_t)N * 16 + (ntile + 1) * 8 + (R + 1) * 8 +
-                       n_tile_pairs * 16 + n_pairs * 44 + (rays ? R * 12 + (ntile + 1) * 8 : 0));
+  a->n_ray_pairs = -1;   // read from the device on demand (mvp_accel_get_info)
+  a->pair_capacity = capacity;
+  a->bytes = (int64_t)(n_views * sizeof(DevCam) + 3 * (size_t)N * 16 + 2 * (ntile + 1) * 8 + R * 16 +
+                       kNumCounters * 8 + n_tile_pairs * (4 + 4 + 48 + 8 + 16 + 4) + (size_t)N * 24 + capacity * 24 +
+                       (rays ? R * 12 + (ntile + 1) * 8 : 0));
   a->blocks = keep.list;
   keep.keep = true;
-  // temporaries are recycled once the emit kernel has run
+  // temporaries are recycled once the pairs kernel has run
   MVP_CHECK(ctx->arena.release_after(temp.list, s));
   temp.keep = true;
   guard.keep = true;
@@ -406,6 +418,7 @@ mvp_status destroy_accel(mvp_ctx *ctx, mvp_accel *a, hipStream_t s) {
   if (!ctx || !a || a->ctx != ctx) { set_error("bad accel handle"); return MVP_ERR_INVALID; }
   mvp_status st = ctx->arena.release_after(a->blocks, s);
   ctx->live_accels.fetch_sub(1);
+  if (a->built) (void)hipEventDestroy(a->built);
   delete a;
   return st;
 }
@@ -511,6 +524,13 @@ mvp_status mvp_accel_destroy(mvp_ctx *ctx, mvp_accel *accel, void *stream) {
 
 mvp_status mvp_accel_get_info(const mvp_accel *a, mvp_accel_info *info) {
   if (!a || !info) { set_error("NULL argument"); return MVP_ERR_INVALID; }
+  if (a->n_ray_pairs < 0) {   // the pairs kernel counts them on the device
+    MVP_HIP(hipSetDevice(a->ctx->device));
+    MVP_HIP(hipEventSynchronize(a->built));
+    uint64_t n = 0;
+    MVP_HIP(hipMemcpy(&n, a->counters + kCntPairs, sizeof n, hipMemcpyDeviceToHost));
+    const_cast<mvp_accel *>(a)->n_ray_pairs = (int64_t)n;
+  }
   info->n_views = a->V; info->width = a->W; info->height = a->H; info->n_prim = a->N;
   info->n_tile_pairs = a->n_tile_pairs; info->n_ray_pairs = a->n_ray_pairs; info->device_bytes = a->bytes;
   return MVP_OK;
@@ -671,7 +691,7 @@ mvp_status mvp_accel_load_counts(mvp_ctx *ctx, const mvp_accel *a, uint64_t *out
   if (!ctx || !a || a->ctx != ctx || !out) { set_error("bad argument"); return MVP_ERR_INVALID; }
   hipStream_t s = (hipStream_t)stream;
   MVP_HIP(hipSetDevice(ctx->device));
-  MVP_HIP(hipMemcpyAsync(out, a->counters, kNumCounters * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  MVP_HIP(hipMemcpyAsync(out, a->counters, (kCntBwdFlush + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   MVP_HIP(hipStreamSynchronize(s));
   return MVP_OK;
 }
@@ -690,15 +710,14 @@ mvp_status mvp_debug_hits(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *pri
   MVP_CHECK(temp.get(&cnt, R));
   MVP_CHECK(temp.get(&scratch, scan_scratch_bytes(R)));
   AccelView av = a->view(prims->M);
-  MVP_HIP(launch_hit_count(av, 1, cnt, nullptr, s));
+  MVP_HIP(launch_hit_count(av, cnt, s));
   MVP_HIP(launch_scan_u32_u64(cnt, (uint64_t *)offsets, R, scratch, s));
   uint64_t total = 0;
   MVP_CHECK(read_u64((const uint64_t *)offsets + R, &total, s));
   *n_total = (int64_t)total;
   if ((int64_t)total > ids_cap) { set_error("ids_cap %lld < %llu hits", (long long)ids_cap, (unsigned long long)total); return MVP_ERR_OOM; }
   if (total > 0 && !ids) { set_error("ids is NULL"); return MVP_ERR_INVALID; }
-  av.ray_off = (const uint64_t *)offsets;
-  MVP_HIP(launch_hit_emit(av, 1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, ids, s));
+  MVP_HIP(launch_hit_ids(av, (const uint64_t *)offsets, ids, s));
   MVP_HIP(hipStreamSynchronize(s));
   return MVP_OK;
 }

@@ -84,11 +84,17 @@ struct mvp_accel {
   uint64_t *item_off = nullptr;
   int64_t n_items_max = 0;             // upper bound on the backward work items
   int32_t item_entries = 64;           // culling-list entries per backward work item
-  uint64_t *entry_off = nullptr;
-  uint32_t *entry_pairs = nullptr;
-  uint64_t *ray_off = nullptr;
-  float4 *pa = nullptr, *pb = nullptr;
-  int2 *pj = nullptr;
+  float4 *ef = nullptr;                // entry frames
+  uint64_t *pair_base = nullptr;       // per tile
+  uint64_t *ray_seg = nullptr;         // per ray slot
+  int2 *ray_nj = nullptr;              // per ray slot
+  int4 *pr = nullptr;                  // pair records
+  uint64_t *ent_base = nullptr;        // per culling-list entry
+  uint32_t *ent_n = nullptr;
+  uint32_t *ent_tile = nullptr;
+  uint2 *ent_rec = nullptr;            // per-entry pair lists
+  uint64_t pair_capacity = 0;
+  hipEvent_t built = nullptr;          // recorded when the build's kernels have been enqueued
   int64_t n_slots = 0;                 // rays: V*H*W (full frames) or the subset size
   int64_t *ray_pix = nullptr;          // subset only: pixel id of each ray slot
   uint64_t *tile_ray_off = nullptr;    // subset only
@@ -106,8 +112,8 @@ struct mvp_accel {
     v.cams = cams; v.xf = xf; v.tile_off = tile_off; v.tile_list = tile_list;
     v.prim_entry_off = prim_entry_off; v.prim_entries = prim_entries; v.item_off = item_off;
     v.item_entries = item_entries;
-    v.entry_off = entry_off; v.entry_pairs = entry_pairs;
-    v.ray_off = ray_off; v.pa = pa; v.pb = pb; v.pj = pj;
+    v.ef = ef; v.pair_base = pair_base; v.ray_seg = ray_seg; v.ray_nj = ray_nj; v.pr = pr;
+    v.ent_base = ent_base; v.ent_n = ent_n; v.ent_tile = ent_tile; v.ent_rec = ent_rec;
     v.n_slots = n_slots; v.ray_pix = ray_pix; v.tile_ray_off = tile_ray_off; v.tile_rays = tile_rays;
     return v;
   }

@@ -12,12 +12,14 @@
 //   tile_fill  writes each primitive into the culling list of every tile of its
 //              rectangle.  These lists take the role of the paper's per-frame
 //              BVH (Sec. 3.2.1): a ray only looks at its tile's list.
-//   hit_count/ per ray: slab test against every primitive of the tile's list
-//   hit_emit   (staged in LDS), then the fixed-step sample interval [jlo, jhi]
+//   pairs      per ray: slab test against every primitive of the tile's list
+//              (staged in LDS), then the fixed-step sample interval [jlo, jhi]
 //              inside each hit box.  The resulting per-ray list of
-//              (primitive, local ray, sample interval), sorted by (jlo, id), is
-//              the "primitives each ray intersects" and their domain of
-//              integration (Sec. 3.2.1).
+//              (sample interval, list position), sorted by first sample and
+//              then primitive id, is the "primitives each ray intersects" and
+//              their domain of integration (Sec. 3.2.1); the local ray of a
+//              pair is rebuilt from its entry's frame (A, a = A (o - t)) and
+//              b = A d.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -162,36 +164,6 @@ hipError_t launch_scan_u32_u64(const uint32_t *in, uint64_t *out, size_t n, void
 // canonical FP32 geometry (one rounding per written operation)
 // ---------------------------------------------------------------------------
 
-// Unit direction of the ray through the centre of pixel (px, py).
-__device__ inline void pixel_ray(const DevCam &c, int px, int py, float d[3]) {
-  const float u = (float)px + 0.5f;
-  const float v = (float)py + 0.5f;
-  float e[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    float t0 = c.P[3 * i + 0] * u;
-    float t1 = c.P[3 * i + 1] * v;
-    float t2 = t0 + t1;
-    e[i] = t2 + c.P[3 * i + 2];
-  }
-  float s0 = e[0] * e[0];
-  float s1 = e[1] * e[1];
-  float s2 = e[2] * e[2];
-  float n2 = (s0 + s1) + s2;
-  float nrm = sqrtf(n2);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) d[i] = e[i] / nrm;
-}
-
-// r = M v for one row (Mr0, Mr1, Mr2): fl(fl(fl(M0 v0) + fl(M1 v1)) + fl(M2 v2))
-__device__ inline float row_dot(float m0, float m1, float m2, const float v[3]) {
-  float p0 = m0 * v[0];
-  float p1 = m1 * v[1];
-  float p2 = m2 * v[2];
-  float s = p0 + p1;
-  return s + p2;
-}
-
 // Slab test of the local ray y(t) = a + t b against [-1,1]^3, clipped to t >= t_near.
 __device__ inline bool slab_test(const float a[3], const float b[3], float t_near, float *t_in,
                                  float *t_out) {
@@ -254,7 +226,7 @@ __global__ __launch_bounds__(256) void k_prep(int N, const float *__restrict__ p
                                               const float *__restrict__ rot,
                                               const float *__restrict__ scale, AccelView av,
                                               float4 *__restrict__ xf, int4 *__restrict__ rect,
-                                              uint32_t *__restrict__ tile_cnt) {
+                                              uint32_t *__restrict__ depth, uint32_t *__restrict__ tile_cnt) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
   float R[9], s[3], t[3];
@@ -331,6 +303,13 @@ __global__ __launch_bounds__(256) void k_prep(int N, const float *__restrict__ p
       else r = make_int4(px0 / kTile, py0 / kTile, px1 / kTile, py1 / kTile);
     }
     rect[(size_t)v * N + k] = r;
+    // order key of the box along the rays of this view: its distance from the
+    // camera less its half diagonal (a lower bound of where rays enter it),
+    // as float bits mapped to an unsigned order
+    const float dk = sqrtf(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]) -
+                     sqrtf(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    const uint32_t bits = __float_as_uint(dk);
+    depth[(size_t)v * N + k] = (bits & 0x80000000u) ? ~bits : (bits | 0x80000000u);
     if (r.x <= r.z && r.y <= r.w) {
       for (int ty = r.y; ty <= r.w; ++ty)
         for (int tx = r.x; tx <= r.z; ++tx)
@@ -339,11 +318,11 @@ __global__ __launch_bounds__(256) void k_prep(int N, const float *__restrict__ p
   }
 }
 
-hipError_t launch_prep(const mvp_prims &p, const AccelView &av, float4 *xf, int4 *rect,
+hipError_t launch_prep(const mvp_prims &p, const AccelView &av, float4 *xf, int4 *rect, uint32_t *depth,
                        uint32_t *tile_cnt, hipStream_t s) {
   if (p.n_prim == 0) return hipSuccess;
   hipLaunchKernelGGL(k_prep, dim3((p.n_prim + 255) / 256), dim3(256), 0, s, p.n_prim, p.pos, p.rot,
-                     p.scale, av, xf, rect, tile_cnt);
+                     p.scale, av, xf, rect, depth, tile_cnt);
   return hipGetLastError();
 }
 
@@ -380,16 +359,33 @@ __global__ __launch_bounds__(256) void k_prim_entry_count(const uint32_t *__rest
   for (; g < n; g += stride) atomicAdd(&cnt[list[g]], 1u);
 }
 
-__global__ __launch_bounds__(256) void k_prim_entry_fill(const uint32_t *__restrict__ list, uint64_t n,
-                                                         const uint64_t *__restrict__ off,
-                                                         uint32_t *__restrict__ cursor,
-                                                         uint32_t *__restrict__ out) {
+// Transposed lists without atomics: the entries of primitive k come from the
+// tiles of its screen rectangles, view by view and row by row, so the place of
+// entry g (tile (v, tx, ty), primitive k) in k's list follows from the
+// rectangles alone and the lists come out ascending in g.
+__global__ __launch_bounds__(256) void k_prim_entry_place(AccelView av, const int4 *__restrict__ rect, uint64_t n,
+                                                          const uint64_t *__restrict__ off,
+                                                          uint32_t *__restrict__ out) {
+  const int T = av.tiles_x * av.tiles_y;
   uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (; g < n; g += stride) {
-    const uint32_t k = list[g];
-    const uint64_t pos = off[k] + atomicAdd(&cursor[k], 1u);
-    if (pos < off[k + 1]) out[pos] = (uint32_t)g;
+    // tile of entry g: last tile t with tile_off[t] <= g
+    int lo = 0, hi = av.V * T - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (av.tile_off[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    const int v = lo / T, tt = lo - v * T, tx = tt % av.tiles_x, ty = tt / av.tiles_x;
+    const uint32_t k = av.tile_list[g];
+    uint64_t p = 0;
+    for (int w = 0; w < v; ++w) {
+      const int4 r = rect[(size_t)w * av.N + k];
+      if (r.x <= r.z && r.y <= r.w) p += (uint64_t)(r.z - r.x + 1) * (uint64_t)(r.w - r.y + 1);
+    }
+    const int4 r = rect[(size_t)v * av.N + k];
+    p += (uint64_t)(ty - r.y) * (uint64_t)(r.z - r.x + 1) + (uint64_t)(tx - r.x);
+    out[off[k] + p] = (uint32_t)g;
   }
 }
 
@@ -405,11 +401,10 @@ hipError_t launch_prim_entry_count(const uint32_t *tile_list, uint64_t n, uint32
   return hipGetLastError();
 }
 
-hipError_t launch_prim_entry_fill(const uint32_t *tile_list, uint64_t n, const uint64_t *off, uint32_t *cursor,
-                                  uint32_t *prim_entries, hipStream_t s) {
+hipError_t launch_prim_entry_place(const AccelView &av, const int4 *rect, uint64_t n, const uint64_t *off,
+                                   uint32_t *prim_entries, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prim_entry_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, tile_list, n, off, cursor,
-                     prim_entries);
+  hipLaunchKernelGGL(k_prim_entry_place, dim3(grid_for(n, 256)), dim3(256), 0, s, av, rect, n, off, prim_entries);
   return hipGetLastError();
 }
 
@@ -421,31 +416,38 @@ hipError_t launch_item_count(const uint64_t *prim_entry_off, int n_prim, int per
   return hipGetLastError();
 }
 
-// Sort every tile's culling list by primitive id, so that the list order (and
-// with it the order of every per-ray list and of every floating-point sum over
-// a sample's primitives) does not depend on the order of the fill atomics.
-// Bitonic sort in LDS; lists longer than kSortMax fall back to a heapsort by
-// one thread.
+// Sort segments [off[i], off[i+1]) of 32-bit values ascending: plain values
+// (depth == nullptr), or culling-list entries (primitive ids) of segment =
+// tile i by (depth[v N + id], id) with v = i / tiles_per_view, so that each
+// tile's list runs from near to far and a ray meets its primitives nearly in
+// the order of their first samples; ties and the order itself are
+// independent of the order of the fill atomics.  Bitonic sort in LDS;
+// segments longer than kSortMax fall back to a heapsort by one thread.
 constexpr int kSortMax = 4096;
 
-__global__ __launch_bounds__(256) void k_segment_sort(const uint64_t *__restrict__ off,
-                                                      uint32_t *__restrict__ list) {
-  __shared__ uint32_t s[kSortMax];
+__device__ __forceinline__ uint64_t sort_key(uint32_t x, const uint32_t *depth, uint64_t vN) {
+  return depth ? ((uint64_t)depth[vN + x] << 32) | x : (uint64_t)x;
+}
+
+__global__ __launch_bounds__(256) void k_segment_sort(const uint64_t *__restrict__ off, uint32_t *__restrict__ list,
+                                                      const uint32_t *__restrict__ depth, int N, int tiles_per_view) {
+  __shared__ uint64_t s[kSortMax];
   const int64_t seg = blockIdx.x;
   const uint64_t b = off[seg];
   const int64_t n = (int64_t)(off[seg + 1] - b);
   if (n < 2) return;
+  const uint64_t vN = depth ? (uint64_t)(seg / tiles_per_view) * (uint64_t)N : 0;
   if (n <= kSortMax) {
     int np = 2;
     while (np < n) np <<= 1;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) s[i] = i < n ? list[b + i] : 0xffffffffu;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s[i] = i < n ? sort_key(list[b + i], depth, vN) : ~0ull;
     __syncthreads();
     for (int k = 2; k <= np; k <<= 1) {
       for (int j = k >> 1; j > 0; j >>= 1) {
         for (int i = threadIdx.x; i < np; i += blockDim.x) {
           const int ixj = i ^ j;
           if (ixj > i) {
-            const uint32_t x = s[i], y = s[ixj];
+            const uint64_t x = s[i], y = s[ixj];
             const bool up = (i & k) == 0;
             if ((x > y) == up) {
               s[i] = y;
@@ -456,16 +458,17 @@ __global__ __launch_bounds__(256) void k_segment_sort(const uint64_t *__restrict
         __syncthreads();
       }
     }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) list[b + i] = s[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) list[b + i] = (uint32_t)s[i];
     return;
   }
   if (threadIdx.x != 0) return;
   uint32_t *a = list + b;
+  auto key = [&](int64_t i) { return sort_key(a[i], depth, vN); };
   auto sift = [&](int64_t root, int64_t end) {
     while (2 * root + 1 < end) {
       int64_t child = 2 * root + 1;
-      if (child + 1 < end && a[child] < a[child + 1]) ++child;
-      if (a[root] < a[child]) {
+      if (child + 1 < end && key(child) < key(child + 1)) ++child;
+      if (key(root) < key(child)) {
         const uint32_t t = a[root]; a[root] = a[child]; a[child] = t;
         root = child;
       } else {
@@ -480,9 +483,10 @@ __global__ __launch_bounds__(256) void k_segment_sort(const uint64_t *__restrict
   }
 }
 
-hipError_t launch_segment_sort(const uint64_t *off, uint32_t *data, int64_t n_seg, hipStream_t s) {
+hipError_t launch_segment_sort(const uint64_t *off, uint32_t *data, int64_t n_seg, const uint32_t *depth, int N,
+                               int tiles_per_view, hipStream_t s) {
   if (n_seg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_segment_sort, dim3((unsigned)n_seg), dim3(256), 0, s, off, data);
+  hipLaunchKernelGGL(k_segment_sort, dim3((unsigned)n_seg), dim3(256), 0, s, off, data, depth, N, tiles_per_view);
   return hipGetLastError();
 }
 
@@ -584,19 +588,162 @@ __device__ inline bool pair_of(const Staged &sm, int e, const float d[3], float 
 }
 
 
-// Count kernel: per ray the number of pairs (mode 0: pairs with >= 1 sample;
-// mode 1: slab hits), and in mode 0 per culling-list entry the number of the
-// tile's rays that form a pair with it (entry_cnt, indexed like tile_list).
-__global__ __launch_bounds__(kTileThreads) void k_hit_count(AccelView av, int mode,
-                                                             uint32_t *__restrict__ ray_cnt,
-                                                             uint32_t *__restrict__ entry_cnt) {
+// Pair capacity of every tile: its culling-list length times its rays.
+__global__ __launch_bounds__(256) void k_tile_capacity(const uint32_t *__restrict__ tile_cnt,
+                                                       const uint32_t *__restrict__ tile_rays_cnt, size_t ntile,
+                                                       uint32_t *__restrict__ cap) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ntile) {   // saturated, so that a product beyond 32 bits cannot wrap to a small capacity
+    const uint64_t c = (uint64_t)tile_cnt[t] * (tile_rays_cnt ? tile_rays_cnt[t] : (uint32_t)kTileThreads);
+    cap[t] = (uint32_t)min<uint64_t>(c, 0xffffffffull);
+  }
+}
+
+hipError_t launch_tile_capacity(const uint32_t *tile_cnt, const uint32_t *tile_rays_cnt, size_t ntile, uint32_t *cap,
+                                hipStream_t s) {
+  if (ntile == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_capacity, dim3((unsigned)((ntile + 255) / 256)), dim3(256), 0, s, tile_cnt,
+                     tile_rays_cnt, ntile, cap);
+  return hipGetLastError();
+}
+
+// Pairs kernel, one workgroup per screen tile, one thread per ray.  The tile's
+// culling list (ordered near to far) is staged through LDS in chunks of
+// kStage entries; every ray runs the canonical slab test against each staged
+// entry, and each pair with at least one sample is inserted into the ray's
+// slots in (jlo, primitive id) order.  The list order leaves few pairs out of
+// place, and those only by a few places, so the ray keeps its last kTail
+// pairs sorted in registers and writes a pair to device memory once kTail
+// later ones have arrived; a pair that belongs before all of those moves the
+// written ones up by one.  The same pair is listed under its entry in ray
+// order: the rays of each wave that hit the entry are ranked by a ballot into
+// the wave's 64 slots of the entry's list.  The staging threads also write
+// the entries' frames.
+constexpr int kTail = 4;
+
+__device__ __forceinline__ bool pair_before(const int4 &a, const int4 &b) {
+  return a.x < b.x || (a.x == b.x && a.w < b.w);
+}
+
+__global__ __launch_bounds__(kTileThreads) void k_pairs(AccelView av, float4 *__restrict__ ef,
+                                                         int4 *__restrict__ pr, uint64_t *__restrict__ ray_seg,
+                                                         int2 *__restrict__ ray_nj, uint64_t *__restrict__ ent_base,
+                                                         uint32_t *__restrict__ ent_n, uint32_t *__restrict__ ent_tile,
+                                                         uint2 *__restrict__ ent_rec,
+                                                         unsigned long long *__restrict__ n_pairs) {
   __shared__ Staged sm;
-  __shared__ uint32_t s_cnt[kTileThreads / kWave][kStage];
+  const int tile = blockIdx.x;
+  const int t = threadIdx.x;
+  int v, px, py;
+  size_t ray;
+  const bool valid = tile_ray(av, tile, t, &ray, &v, &px, &py);
+  const int lane = t & (kWave - 1), wave = t / kWave;
+  const DevCam &cam = av.cams[v];
+  float d[3];
+  pixel_ray(cam, px, py, d);
+  const uint64_t lb = av.tile_off[tile], le = av.tile_off[tile + 1];
+  const uint64_t len = le - lb;
+  const uint64_t rays = av.tile_rays ? av.tile_ray_off[tile + 1] - av.tile_ray_off[tile] : (uint64_t)kTileThreads;
+  const uint64_t seg = av.pair_base[tile] + (uint64_t)t * len;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  int nw = 0;         // pairs written to device memory, in order
+  int nt = 0;         // pairs in the sorted register tail, all after the written ones
+  int4 tb[kTail];
+#pragma unroll
+  for (int q = 0; q < kTail; ++q) tb[q] = make_int4(0, 0, 0, 0);
+  int4 wl = make_int4(INT_MIN, 0, 0, INT_MIN);   // the last written pair (its key)
+  for (uint64_t c0 = lb; c0 < le; c0 += kStage) {
+    const int nc = (int)min<uint64_t>(kStage, le - c0);
+    __syncthreads();
+    stage_chunk(sm, av, cam, c0, nc);
+    if (t < nc) {   // the entry's frame and where its pair list goes
+      const uint64_t g = c0 + t;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) ef[3 * g + r] = make_float4(sm.A[3 * r][t], sm.A[3 * r + 1][t], sm.A[3 * r + 2][t], sm.a[r][t]);
+      ent_base[g] = av.pair_base[tile] + (g - lb) * rays;
+      ent_tile[g] = (uint32_t)tile;
+    }
+    __syncthreads();
+    for (int e = 0; e < nc; ++e) {
+      float a[3], b[3];
+      int jlo = 0, jhi = 0;
+      const bool hit = valid && pair_of(sm, e, d, av.t_near, av.step, 0, a, b, &jlo, &jhi);
+      const unsigned long long m = __ballot(hit);
+      const uint64_t g = c0 + e;
+      if (hit) {
+        const int4 rec = make_int4(jlo, jhi, (int)(g - lb), sm.id[e]);
+        if (nw > 0 && pair_before(rec, wl)) {
+          // before every written pair still after it: those move up by one
+          int at = nw;
+          while (at > 0) {
+            const int4 p = pr[seg + at - 1];
+            if (!pair_before(rec, p)) break;
+            pr[seg + at] = p;
+            --at;
+          }
+          pr[seg + at] = rec;
+          ++nw;
+        } else if (nt == kTail && pair_before(rec, tb[0])) {   // after the written pairs, before the tail
+          pr[seg + nw] = rec;
+          wl = rec;
+          ++nw;
+        } else {
+          if (nt == kTail) {   // the tail is full: its first pair is final among the written ones
+            pr[seg + nw] = tb[0];
+            wl = tb[0];
+            ++nw;
+#pragma unroll
+            for (int q = 0; q < kTail - 1; ++q) tb[q] = tb[q + 1];
+            --nt;
+          }
+#pragma unroll
+          for (int q = 0; q < kTail; ++q)
+            if (q == nt) tb[q] = rec;
+#pragma unroll
+          for (int q = kTail - 1; q > 0; --q)   // sink the new pair to its place
+            if (q <= nt && pair_before(tb[q], tb[q - 1])) {
+              const int4 x = tb[q];
+              tb[q] = tb[q - 1];
+              tb[q - 1] = x;
+            }
+          ++nt;
+        }
+        ent_rec[av.pair_base[tile] + (g - lb) * rays + (uint64_t)wave * kWave + (uint32_t)__popcll(m & lt)] =
+            make_uint2((uint32_t)jlo | ((uint32_t)t << 24), (uint32_t)jhi);
+      }
+      if (lane == 0) ent_n[4 * g + wave] = (uint32_t)__popcll(m);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kTail; ++q)
+    if (q < nt) pr[seg + nw + q] = tb[q];
+  const int i = nw + nt;
+  if (valid) {
+    ray_seg[ray] = seg;
+    ray_nj[ray] = make_int2(i, i ? (nw ? pr[seg].x : tb[0].x) : INT_MAX);
+  }
+  const unsigned long long c = wave_sum_u64((unsigned long long)i);
+  if (lane == 0 && c) atomicAdd(n_pairs, c);
+}
+
+hipError_t launch_pairs(const AccelView &av, float4 *ef, int4 *pr, uint64_t *ray_seg, int2 *ray_nj,
+                        uint64_t *ent_base, uint32_t *ent_n, uint32_t *ent_tile, uint2 *ent_rec,
+                        unsigned long long *n_pairs, hipStream_t s) {
+  const int ntile = av.V * av.tiles_x * av.tiles_y;
+  if (ntile == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pairs, dim3(ntile), dim3(kTileThreads), 0, s, av, ef, pr, ray_seg, ray_nj, ent_base,
+                     ent_n, ent_tile, ent_rec, n_pairs);
+  return hipGetLastError();
+}
+
+// Debug hit sets: per ray the number of slab hits against its tile's list
+// (with or without samples).
+__global__ __launch_bounds__(kTileThreads) void k_hit_count(AccelView av, uint32_t *__restrict__ ray_cnt) {
+  __shared__ Staged sm;
   const int tile = blockIdx.x;
   int v, px, py;
   size_t slot;
   const bool valid = tile_ray(av, tile, threadIdx.x, &slot, &v, &px, &py);
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const DevCam &cam = av.cams[v];
   float d[3];
   pixel_ray(cam, px, py, d);
@@ -610,202 +757,59 @@ __global__ __launch_bounds__(kTileThreads) void k_hit_count(AccelView av, int mo
     for (int e = 0; e < n; ++e) {
       float a[3], b[3];
       int jlo, jhi;
-      const bool hit = valid && pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi);
-      cnt += hit ? 1u : 0u;
-      if (mode == 0) {
-        const unsigned long long m = __ballot(hit);
-        if (lane == 0) s_cnt[wave][e] = (uint32_t)__popcll(m);
-      }
-    }
-    if (mode == 0) {
-      __syncthreads();
-      if ((int)threadIdx.x < n) {
-        uint32_t tot = 0;
-#pragma unroll
-        for (int w = 0; w < kTileThreads / kWave; ++w) tot += s_cnt[w][threadIdx.x];
-        entry_cnt[c0 + threadIdx.x] = tot;
-      }
+      cnt += (valid && pair_of(sm, e, d, av.t_near, av.step, 1, a, b, &jlo, &jhi)) ? 1u : 0u;
     }
   }
   if (valid) ray_cnt[slot] = cnt;
 }
 
-hipError_t launch_hit_count(const AccelView &av, int mode, uint32_t *ray_cnt, uint32_t *entry_cnt,
-                            hipStream_t s) {
+hipError_t launch_hit_count(const AccelView &av, uint32_t *ray_cnt, hipStream_t s) {
   const int ntile = av.V * av.tiles_x * av.tiles_y;
   if (ntile == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hit_count, dim3(ntile), dim3(kTileThreads), 0, s, av, mode, ray_cnt, entry_cnt);
+  hipLaunchKernelGGL(k_hit_count, dim3(ntile), dim3(kTileThreads), 0, s, av, ray_cnt);
   return hipGetLastError();
 }
 
-// Emit kernel, three passes over the tile's culling list (staged in LDS in
-// chunks).  Pass 1 finds the ray's pairs (the slab tests of the count pass,
-// same predicate) and keeps their first samples jlo in list order, which is
-// primitive-id order.  Pass 2 ranks each pair by (jlo, list position), the
-// order the forward marches them in: in LDS for lists of at most kKeys pairs
-// (jlo < 2^24 in the low 24 bits, the rank in the top 8), in device memory
-// (tkey/trank) for longer ones.  Pass 3 writes every pair to its ranked slot of
-// the ray's segment [ray_off[ray], ray_off[ray+1]):
-//   pa = (a, primitive id), pb = (b, ray index), pj = (jlo, jhi),
-// and lists it under its culling-list entry (entry_pairs[entry_off[g] ..],
-// pixel order) for the backward.  When the whole culling list fits one LDS
-// chunk (the common case) it stays staged, and a ray with a short list
-// recomputes its pairs in rank order and writes its segment front to back, so
-// each output line is completed in one burst instead of piece by piece.  Mode
-// 1 writes only the primitive ids of the slab hits into `ids`, in primitive-id
-// order.
-constexpr int kKeys = 24;
-
-__global__ __launch_bounds__(kTileThreads) void k_hit_emit(AccelView av, int mode, int32_t *__restrict__ tkey,
-                                                            uint32_t *__restrict__ trank, float4 *__restrict__ pa,
-                                                            float4 *__restrict__ pb, int2 *__restrict__ pj,
-                                                            uint32_t *__restrict__ entry_pairs,
-                                                            int32_t *__restrict__ ids) {
+// ... and their primitive ids in increasing order at ids[off[ray] ..] (each
+// id inserted into the ray's sorted run as it is found).
+__global__ __launch_bounds__(kTileThreads) void k_hit_ids(AccelView av, const uint64_t *__restrict__ off,
+                                                           int32_t *__restrict__ ids) {
   __shared__ Staged sm;
-  __shared__ uint32_t s_bits[kStage / 32][kTileThreads];
-  __shared__ uint32_t s_cnt[kTileThreads / kWave][kStage];
-  __shared__ uint32_t s_key[kKeys][kTileThreads];
-  __shared__ uint8_t s_ent[kKeys][kTileThreads];   // single-chunk lists: entry of the i-th pair
-  __shared__ uint8_t s_inv[kKeys][kTileThreads];   // ... and of the pair of rank r
   const int tile = blockIdx.x;
-  const int t = threadIdx.x;
   int v, px, py;
-  size_t ray;
-  const bool valid = tile_ray(av, tile, t, &ray, &v, &px, &py);
-  const int lane = t & (kWave - 1), wave = t / kWave;
+  size_t slot;
+  const bool valid = tile_ray(av, tile, threadIdx.x, &slot, &v, &px, &py);
   const DevCam &cam = av.cams[v];
   float d[3];
   pixel_ray(cam, px, py, d);
-  const uint64_t out0 = valid ? av.ray_off[ray] : 0;
-  const int n = valid ? (int)(av.ray_off[ray + 1] - out0) : 0;   // same predicate as the count pass
-  const bool in_lds = n <= kKeys;
   const uint64_t lb = av.tile_off[tile], le = av.tile_off[tile + 1];
-  const bool single = le - lb <= (uint64_t)kStage;                 // the same for the whole workgroup
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  // pass 1: first samples (or, in mode 1, primitive ids) in list order
-  int i = 0;
+  const uint64_t o0 = valid ? off[slot] : 0;
+  uint64_t o = o0;
   for (uint64_t c0 = lb; c0 < le; c0 += kStage) {
-    const int nc = (int)min<uint64_t>(kStage, le - c0);
+    const int n = (int)min<uint64_t>(kStage, le - c0);
     __syncthreads();
-    stage_chunk(sm, av, cam, c0, nc);
+    stage_chunk(sm, av, cam, c0, n);
     __syncthreads();
-    uint32_t word = 0;
-    for (int e = 0; e < nc; ++e) {
+    for (int e = 0; e < n; ++e) {
       float a[3], b[3];
-      int jlo = 0, jhi = 0;
-      if (i < n && pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi)) {
-        if (mode != 0) {
-          ids[out0 + i] = sm.id[e];
-        } else if (in_lds) {
-          s_key[i][t] = (uint32_t)jlo;
-          s_ent[i][t] = (uint8_t)e;
-        } else {
-          tkey[out0 + i] = jlo;
+      int jlo, jhi;
+      if (valid && pair_of(sm, e, d, av.t_near, av.step, 1, a, b, &jlo, &jhi)) {
+        const int32_t id = sm.id[e];
+        uint64_t at = o++;
+        while (at > o0 && ids[at - 1] > id) {
+          ids[at] = ids[at - 1];
+          --at;
         }
-        ++i;
-        word |= 1u << (e & 31);
-      }
-      if (single && ((e & 31) == 31 || e == nc - 1)) {
-        s_bits[e >> 5][t] = word;
-        word = 0;
-      }
-    }
-  }
-  if (mode != 0) return;
-  // pass 2: rank of each pair by (jlo, list position), 8 pairs at a time
-  for (int i0 = 0; i0 < n; i0 += 8) {
-    int key[8], rank[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      key[q] = i0 + q < n ? (in_lds ? (int)(s_key[i0 + q][t] & 0xffffffu) : tkey[out0 + i0 + q]) : INT_MAX;
-      rank[q] = 0;
-    }
-    for (int j = 0; j < n; ++j) {
-      const int kj = in_lds ? (int)(s_key[j][t] & 0xffffffu) : tkey[out0 + j];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) rank[q] += (kj < key[q] || (kj == key[q] && j < i0 + q)) ? 1 : 0;
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      if (i0 + q < n) {
-        if (in_lds) {
-          s_key[i0 + q][t] = (uint32_t)key[q] | ((uint32_t)rank[q] << 24);
-          s_inv[rank[q]][t] = s_ent[i0 + q][t];
-        } else {
-          trank[out0 + i0 + q] = (uint32_t)rank[q];
-        }
-      }
-    }
-  }
-  // pass 3: every pair to its ranked slot, and the per-entry pair lists
-  i = 0;
-  for (uint64_t c0 = lb; c0 < le; c0 += kStage) {
-    const int nc = (int)min<uint64_t>(kStage, le - c0);
-    if (!single) {
-      __syncthreads();
-      stage_chunk(sm, av, cam, c0, nc);
-      __syncthreads();
-    }
-    const int ic = i;
-    if (single && in_lds) {
-      // the list is still staged: recompute the pairs in rank order
-      for (int r = 0; r < n; ++r) {
-        const int e = s_inv[r][t];
-        float a[3], b[3];
-        int jlo = 0, jhi = 0;
-        (void)pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi);
-        const uint64_t dst = out0 + r;
-        pa[dst] = make_float4(a[0], a[1], a[2], __int_as_float(sm.id[e]));
-        pb[dst] = make_float4(b[0], b[1], b[2], __int_as_float((int)ray));
-        pj[dst] = make_int2(jlo, jhi);
-      }
-      i = n;
-    } else {
-      uint32_t word = 0;
-      for (int e = 0; e < nc; ++e) {
-        float a[3], b[3];
-        int jlo = 0, jhi = 0;
-        if (i < n && pair_of(sm, e, d, av.t_near, av.step, mode, a, b, &jlo, &jhi)) {
-          const uint64_t dst = out0 + (in_lds ? (s_key[i][t] >> 24) : trank[out0 + i]);
-          pa[dst] = make_float4(a[0], a[1], a[2], __int_as_float(sm.id[e]));
-          pb[dst] = make_float4(b[0], b[1], b[2], __int_as_float((int)ray));
-          pj[dst] = make_int2(jlo, jhi);
-          ++i;
-          word |= 1u << (e & 31);
-        }
-        if (!single && ((e & 31) == 31 || e == nc - 1)) {
-          s_bits[e >> 5][t] = word;
-          word = 0;
-        }
-      }
-    }
-    for (int e = 0; e < nc; ++e) {
-      const bool bit = (s_bits[e >> 5][t] >> (e & 31)) & 1u;
-      const unsigned long long m = __ballot(bit);
-      if (lane == 0) s_cnt[wave][e] = (uint32_t)__popcll(m);
-    }
-    __syncthreads();
-    int ii = ic;
-    for (int e = 0; e < nc; ++e) {
-      const bool bit = (s_bits[e >> 5][t] >> (e & 31)) & 1u;
-      const unsigned long long m = __ballot(bit);
-      if (bit) {
-        uint32_t base = 0;
-        for (int q = 0; q < wave; ++q) base += s_cnt[q][e];
-        const uint64_t pos = av.entry_off[c0 + e] + base + (uint32_t)__popcll(m & lt);
-        entry_pairs[pos] = (uint32_t)(out0 + (in_lds ? (s_key[ii][t] >> 24) : trank[out0 + ii]));
-        ++ii;
+        ids[at] = id;
       }
     }
   }
 }
 
-hipError_t launch_hit_emit(const AccelView &av, int mode, int32_t *tkey, uint32_t *trank, float4 *pa, float4 *pb,
-                           int2 *pj, uint32_t *entry_pairs, int32_t *ids, hipStream_t s) {
+hipError_t launch_hit_ids(const AccelView &av, const uint64_t *off, int32_t *ids, hipStream_t s) {
   const int ntile = av.V * av.tiles_x * av.tiles_y;
   if (ntile == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hit_emit, dim3(ntile), dim3(kTileThreads), 0, s, av, mode, tkey, trank, pa, pb, pj,
-                     entry_pairs, ids);
+  hipLaunchKernelGGL(k_hit_ids, dim3(ntile), dim3(kTileThreads), 0, s, av, off, ids);
   return hipGetLastError();
 }
 

@@ -26,15 +26,28 @@ struct DevCam {
 // Everything a kernel needs to address the per-frame structure.
 //
 // Culling lists: tile t (of V*T, view-major) owns tile_list[tile_off[t] ..
-// tile_off[t+1]), primitive ids in increasing order.  Transposed: primitive k
+// tile_off[t+1]), primitive ids ordered near to far (by an order key per view
+// and primitive, then id).  Transposed: primitive k
 // owns the list entries prim_entries[prim_entry_off[k] .. prim_entry_off[k+1])
 // (ascending), grouped into backward work items item_off[k] .. item_off[k+1]
 // of at most item_entries entries each.
-// Pairs: ray r owns pairs [ray_off[r], ray_off[r+1]) sorted by (jlo, id);
-// pair i is (pa[i] = (a, primitive id), pb[i] = (b, ray index),
-// pj[i] = (jlo, jhi)): local ray y(t) = a + t b and its sample interval.
-// entry_pairs[entry_off[g] .. entry_off[g+1]) lists the pairs formed with
-// culling-list entry g (at most one per ray of the tile), in pixel order.
+// Entry frames: culling-list entry g (primitive k in the list of a tile of
+// view v) has ef[3g + i] = (row i of A_k, a_i) with a = A_k (o_v - t_k), the
+// local origin shared by every ray of the view; a ray's local direction is
+// b = A_k d.
+// Pairs: tile t reserves len(t) * R_t pair slots from pair_base[t] (len: its
+// culling-list length; R_t: 256 for full frames, its number of rays for a ray
+// subset), ray number i of the tile the len(t) slots from pair_base[t] +
+// i * len(t).  Ray slot r owns pr[ray_seg[r] .. ray_seg[r] + ray_nj[r].x),
+// its pairs sorted by first sample and then primitive id; pair p is pr[p] =
+// (jlo, jhi, position in the tile's culling list, primitive id), and
+// ray_nj[r].y is the ray's first sample (INT_MAX if none).  The same pairs by culling-list entry, for the backward: entry g at
+// position e of tile t = ent_tile[g] lists the pairs formed with it (at most
+// one per ray of the tile), in ray order, from ent_base[g] = pair_base[t] +
+// e * R_t: the rays of wave w of the tile (ray numbers 64w .. 64w + 63) at
+// ent_rec[ent_base[g] + 64 w .. + ent_n[4g + w]).  A record is
+// (jlo | i << 24, jhi) with i the ray's number in the tile (sample indices
+// stay below 2^24).
 // Per-ray constants of the backward: Tdot, the clamp weight ((1 - T_{S-1}) /
 // sigma_S for the sum rule, 1 - T* for the sequential combine) and the
 // clamping primitive of the sequential combine (-1: none).
@@ -72,12 +85,15 @@ struct AccelView {
   const uint64_t *prim_entry_off;  // [N+1]
   const uint32_t *prim_entries;    // [n_tile_pairs]
   const uint64_t *item_off;        // [N+1]
-  const uint64_t *entry_off;   // [n_tile_pairs+1]
-  const uint32_t *entry_pairs; // [n_pairs]
-  const uint64_t *ray_off;     // [R+1]
-  const float4 *pa;            // [n_pairs]
-  const float4 *pb;            // [n_pairs]
-  const int2 *pj;              // [n_pairs]
+  const float4 *ef;            // [3 n_tile_pairs]
+  const uint64_t *pair_base;   // [V*T+1]
+  const uint64_t *ray_seg;     // [R]
+  const int2 *ray_nj;          // [R]
+  const int4 *pr;              // [pair capacity]
+  const uint64_t *ent_base;    // [n_tile_pairs]
+  const uint32_t *ent_n;       // [4 n_tile_pairs]
+  const uint32_t *ent_tile;    // [n_tile_pairs]
+  const uint2 *ent_rec;        // [pair capacity]
   // Ray slots.  A full frame has one slot per pixel, slot = (v*H + py)*W + px,
   // and ray_pix == tile_rays == nullptr.  A ray subset has n_slots slots;
   // ray_pix[slot] is the pixel of the slot and tile t owns the (at most 256)
@@ -147,6 +163,47 @@ __device__ __forceinline__ bool tile_ray(const AccelView &av, int tile, int t, s
   return true;
 }
 
+// Canonical FP32 geometry shared by the culling kernels and the marches, so
+// that both derive bit-identical pixel rays and local directions (every
+// translation unit is built with -ffp-contract=off: one rounding per written
+// operation).
+// Unit direction of the ray through the centre of pixel (px, py).
+__device__ __forceinline__ void pixel_ray(const DevCam &c, int px, int py, float d[3]) {
+  const float u = (float)px + 0.5f;
+  const float v = (float)py + 0.5f;
+  float e[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    float t0 = c.P[3 * i + 0] * u;
+    float t1 = c.P[3 * i + 1] * v;
+    float t2 = t0 + t1;
+    e[i] = t2 + c.P[3 * i + 2];
+  }
+  float s0 = e[0] * e[0];
+  float s1 = e[1] * e[1];
+  float s2 = e[2] * e[2];
+  float n2 = (s0 + s1) + s2;
+  float nrm = sqrtf(n2);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) d[i] = e[i] / nrm;
+}
+
+// r = M v for one row (Mr0, Mr1, Mr2): fl(fl(fl(M0 v0) + fl(M1 v1)) + fl(M2 v2))
+__device__ __forceinline__ float row_dot(float m0, float m1, float m2, const float v[3]) {
+  float p0 = m0 * v[0];
+  float p1 = m1 * v[1];
+  float p2 = m2 * v[2];
+  float s = p0 + p1;
+  return s + p2;
+}
+
+// Sum over the lanes of a wave.
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
 // Pixel of a ray slot.
 __device__ __forceinline__ void slot_pixel(const AccelView &av, size_t slot, int *v, int *px, int *py) {
   const int64_t pix = av.ray_pix ? av.ray_pix[slot] : (int64_t)slot;
@@ -163,13 +220,14 @@ enum : int {
   kCntRaySamples = 0,   // samples inside >= 1 primitive, up to the stop
   kCntPrimSamples = 1,  // (sample, primitive) pairs: trilinear fetches
   kCntFwdCells = 2,     // forward: voxel-corner sets loaded (8 corners each)
-  kCntFwdPj = 3,        // forward: pair-interval loads (8 B each)
-  kCntFwdPab = 4,       // forward: pair local-ray loads (pa + pb, 32 B each)
+  kCntFwdPj = 3,        // forward: pair-record loads (16 B each)
+  kCntFwdPab = 4,       // forward: entry-frame loads from device memory (52 B each)
   kCntBwdVisit = 5,     // backward: pairs visited by the ordering / bound pass
   kCntBwdReplay = 6,    // backward: pairs replayed
   kCntBwdRuns = 7,      // backward: cell runs (voxel-corner sets loaded)
   kCntBwdFlush = 8,     // backward: non-zero gradient values added to device memory
-  kNumCounters = 9
+  kCntPairs = 9,        // build: (ray, primitive) pairs with at least one sample
+  kNumCounters = 10
 };
 
 // ---- launchers (return the first HIP error) --------------------------------
@@ -179,33 +237,41 @@ hipError_t launch_zero_u64(uint64_t *p, size_t n, hipStream_t s);
 size_t scan_scratch_bytes(size_t n);
 hipError_t launch_scan_u32_u64(const uint32_t *in, uint64_t *out, size_t n, void *scratch, hipStream_t s);
 
-hipError_t launch_prep(const mvp_prims &p, const AccelView &av, float4 *xf, int4 *rect,
+// per primitive: A rows and t (xf), per view its tile rectangle (rect) and an
+// order key along the view's rays (depth); counts tile entries
+hipError_t launch_prep(const mvp_prims &p, const AccelView &av, float4 *xf, int4 *rect, uint32_t *depth,
                        uint32_t *tile_cnt, hipStream_t s);
 hipError_t launch_tile_fill(const AccelView &av, const int4 *rect, uint32_t *cursor,
                             uint32_t *tile_list, hipStream_t s);
-// transpose the culling lists (count per primitive / fill), and count the
-// backward work items of every primitive
+// transpose the culling lists (count per primitive, then place each entry
+// from the rectangles), and count the backward work items of every primitive
 hipError_t launch_prim_entry_count(const uint32_t *tile_list, uint64_t n, uint32_t *cnt, hipStream_t s);
-hipError_t launch_prim_entry_fill(const uint32_t *tile_list, uint64_t n, const uint64_t *off, uint32_t *cursor,
-                                  uint32_t *prim_entries, hipStream_t s);
+hipError_t launch_prim_entry_place(const AccelView &av, const int4 *rect, uint64_t n, const uint64_t *off,
+                                   uint32_t *prim_entries, hipStream_t s);
 hipError_t launch_item_count(const uint64_t *prim_entry_off, int n_prim, int per_item, uint32_t *cnt,
                              hipStream_t s);
 int backward_item_entries(int M);   // culling-list entries per backward work item (<= 64)
-// sort each segment [off[i], off[i+1]) of data (n_seg segments) ascending
-hipError_t launch_segment_sort(const uint64_t *off, uint32_t *data, int64_t n_seg, hipStream_t s);
+// sort each segment [off[i], off[i+1]) of data (n_seg segments) ascending, or
+// with depth: each tile's culling list by (depth[v N + id], id)
+hipError_t launch_segment_sort(const uint64_t *off, uint32_t *data, int64_t n_seg, const uint32_t *depth, int N,
+                               int tiles_per_view, hipStream_t s);
 // ray subsets: count the sampled rays of every tile (flag: 1 = pixel id out of
 // range, 2 = more than 256 rays in a tile), then list them per tile
 hipError_t launch_ray_bin(const AccelView &av, uint32_t *tile_cnt, uint32_t *flag, hipStream_t s);
 hipError_t launch_ray_fill(const AccelView &av, uint32_t *cursor, uint32_t *tile_rays, hipStream_t s);
-// mode 0: (ray, primitive) pairs with >= 1 sample, plus per-entry counts;
-// mode 1: every slab hit (debug), entry_cnt unused
-hipError_t launch_hit_count(const AccelView &av, int mode, uint32_t *ray_cnt, uint32_t *entry_cnt,
-                            hipStream_t s);
-// mode 0 writes the pairs to pa/pb/pj, each ray's sorted by (first sample,
-// primitive id), and the per-entry pair lists; tkey/trank [n_pairs] are
-// scratch for rays with long lists.  Mode 1 writes only ids.
-hipError_t launch_hit_emit(const AccelView &av, int mode, int32_t *tkey, uint32_t *trank, float4 *pa, float4 *pb,
-                           int2 *pj, uint32_t *entry_pairs, int32_t *ids, hipStream_t s);
+// pair capacity of every tile: culling-list length (tile_cnt) times its rays
+// (256, or tile_rays_cnt for a ray subset)
+hipError_t launch_tile_capacity(const uint32_t *tile_cnt, const uint32_t *tile_rays_cnt, size_t ntile, uint32_t *cap,
+                                hipStream_t s);
+// the (ray, primitive) pairs of every ray, the entry frames and the per-entry
+// pair lists (see AccelView); adds the number of pairs to *n_pairs
+hipError_t launch_pairs(const AccelView &av, float4 *ef, int4 *pr, uint64_t *ray_seg, int2 *ray_nj,
+                        uint64_t *ent_base, uint32_t *ent_n, uint32_t *ent_tile, uint2 *ent_rec,
+                        unsigned long long *n_pairs, hipStream_t s);
+// debug hit sets: per ray the number of slab hits (with or without samples),
+// then their primitive ids in increasing order at ids[off[ray] ..]
+hipError_t launch_hit_count(const AccelView &av, uint32_t *ray_cnt, hipStream_t s);
+hipError_t launch_hit_ids(const AccelView &av, const uint64_t *off, int32_t *ids, hipStream_t s);
 
 // bg: optional background [rays,3] composited under the premultiplied colour
 hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, const float *bg, float *rgba,

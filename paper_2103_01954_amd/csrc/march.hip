@@ -111,8 +111,6 @@ __device__ __forceinline__ Cell locate(const float4 &A, const float4 &B, float t
   return c;
 }
 
-__device__ __forceinline__ int jlo_of(const float4 &A) { return __float_as_int(A.w); }
-__device__ __forceinline__ int jhi_of(const float4 &B) { return __float_as_int(B.w); }
 
 // Deterministic in-workgroup compaction of the active pixels of a tile.
 // Returns the number of active pixels; s_list receives their local indices
@@ -135,11 +133,6 @@ __device__ __forceinline__ int compact_tile(bool act, int *s_list, int *s_wave) 
   return total;
 }
 
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
-}
 
 // ---------------------------------------------------------------------------
 // forward
@@ -198,15 +191,63 @@ __device__ __forceinline__ void corner_fade(const float *tab, const Cell &c, flo
   for (int q = 0; q < 8; ++q) wq[q] = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
 }
 
-// RGBA of pair e at tau: trilinear payload of its primitive (opacity times the
-// fade window when FADE).
+// A ray's unit direction, read where it is kept (registers, or a column of
+// LDS with a stride, which frees three registers in the forward march).
+struct Dir {
+  const float *p;
+  int stride;
+  __device__ __forceinline__ void get(float d[3]) const {
+    d[0] = p[0];
+    d[1] = p[stride];
+    d[2] = p[2 * stride];
+  }
+};
+
+// Where a ray finds the frames of its tile's culling-list entries: staged in
+// LDS (four float4 per entry: the three rows of A with a_i in .w, then the
+// primitive id as int bits in .x) or, for long lists, the entry frames in
+// device memory.  local() rebuilds the pair's local ray y(t) = a + t b with
+// b = A d in the build's canonical arithmetic, so sample positions and the
+// pair's sample interval come from the same values.
+struct Frames {
+  const float4 *lds;   // [4 * list length] or nullptr
+  uint64_t lb;         // first culling-list entry of the tile
+  __device__ __forceinline__ void local(const AccelView &av, int pos, const Dir &dir, float4 &A, float4 &B) const {
+    float d[3];
+    dir.get(d);
+    float4 f0, f1, f2;
+    int k;
+    if (lds) {
+      f0 = lds[4 * pos];
+      f1 = lds[4 * pos + 1];
+      f2 = lds[4 * pos + 2];
+      k = __float_as_int(lds[4 * pos + 3].x);
+    } else {
+      const uint64_t g = lb + (uint64_t)pos;
+      f0 = av.ef[3 * g];
+      f1 = av.ef[3 * g + 1];
+      f2 = av.ef[3 * g + 2];
+      k = (int)av.tile_list[g];
+    }
+    A = make_float4(f0.w, f1.w, f2.w, __int_as_float(k));
+    B = make_float4(row_dot(f0.x, f0.y, f0.z, d), row_dot(f1.x, f1.y, f1.z, d), row_dot(f2.x, f2.y, f2.z, d), 0.f);
+  }
+};
+
+// Tile of a ray slot.
+__device__ __forceinline__ int slot_tile(const AccelView &av, size_t slot) {
+  int v, px, py;
+  slot_pixel(av, slot, &v, &px, &py);
+  return (v * av.tiles_y + py / kTile) * av.tiles_x + px / kTile;
+}
+
+// RGBA at tau of the pair with local ray (A, B) (primitive id in A.w):
+// trilinear payload of its primitive (opacity times the fade window when FADE).
 template <bool BF16, bool FADE>
-__device__ __forceinline__ float4 sample_pair(const AccelView &av, const void *pay, const float *fade,
-                                              uint64_t e, float tau) {
+__device__ __forceinline__ float4 sample_pair(const AccelView &av, const void *pay, const float *fade, const float4 &A,
+                                              const float4 &B, float tau) {
   const int M = av.M;
   const float hM = 0.5f * (float)(M - 1);
-  const float4 A = av.pa[e];
-  const float4 B = av.pb[e];
   const Cell c = locate(A, B, tau, M, hM);
   float4 v[8];
   load_corners<BF16>(pay, (size_t)prim_of(A) * M * M * M + c.idx, M, v);
@@ -219,26 +260,8 @@ __device__ __forceinline__ float4 sample_pair(const AccelView &av, const void *p
   return trilerp(v, c);
 }
 
-// Among the pairs [e0, end) (sorted by first sample) that contain sample j,
-// the one with the smallest primitive id above `after`; end if none.
-__device__ __forceinline__ uint64_t next_by_id(const AccelView &av, uint64_t e0, uint64_t end, int j, int after) {
-  int best = INT_MAX;
-  uint64_t be = end;
-  for (uint64_t e = e0; e < end; ++e) {
-    const int2 r = av.pj[e];
-    if (r.x > j) break;
-    if (r.y < j) continue;
-    const int id = prim_of(av.pa[e]);
-    if (id > after && id < best) {
-      best = id;
-      be = e;
-    }
-  }
-  return be;
-}
-
 // Accumulated state of one ray, with its counts of samples and of loads
-// (voxel-corner sets, pair intervals pj, pair local rays pa + pb).
+// (voxel-corner sets, pair records, entry frames read from device memory).
 struct RayState {
   float T = 0.f, I0 = 0.f, I1 = 0.f, I2 = 0.f, t_prev = -1.0f;
   int j_end = -1;
@@ -267,19 +290,38 @@ __device__ __forceinline__ bool composite(RayState &st, int j, float sig, float 
   return true;
 }
 
+// Among the ray's pairs [0, n) (sorted by first sample) that contain sample
+// j, the one with the smallest primitive id above `after`; n if none.
+__device__ __forceinline__ int next_by_id(const AccelView &av, uint32_t seg, int n, int j, int after) {
+  int best = INT_MAX, bi = n;
+  for (int i = 0; i < n; ++i) {
+    const int4 r = av.pr[seg + i];
+    if (r.x > j) break;
+    if (r.y < j) continue;
+    if (r.w > after && r.w < best) {
+      best = r.w;
+      bi = i;
+    }
+  }
+  return bi;
+}
+
 // Sequential combine at sample j, whose summed step saturates: the
 // primitives containing j in increasing id, each with its own clamp step.
-// Pairs containing j all lie in [e0, end).  Returns true to stop.
+// Returns true to stop.
 template <bool BF16, bool FADE>
-__device__ bool seq_sample(const AccelView &av, const void *pay, const float *fade, uint64_t e0, uint64_t end,
-                           int j, RayState &st) {
+__device__ bool seq_sample(const AccelView &av, const Frames &fr, const void *pay, const float *fade, uint32_t seg,
+                           int n, const Dir &d, int j, RayState &st) {
   const float dt = av.step;
   const float tau = (float)j * dt;
   const float T0 = st.T;
   st.j_end = j;
   int last = -1;
-  for (uint64_t e = next_by_id(av, e0, end, j, last); e < end; e = next_by_id(av, e0, end, j, last)) {
-    const float4 s = sample_pair<BF16, FADE>(av, pay, fade, e, tau);
+  for (int i = next_by_id(av, seg, n, j, last); i < n; i = next_by_id(av, seg, n, j, last)) {
+    const int4 r = av.pr[seg + i];
+    float4 A, B;
+    fr.local(av, r.z, d, A, B);
+    const float4 s = sample_pair<BF16, FADE>(av, pay, fade, A, B, tau);
     const float Tn = st.T + s.w * dt;
     if (Tn <= 1.0f) {
       st.T = Tn;
@@ -295,7 +337,7 @@ __device__ bool seq_sample(const AccelView &av, const void *pay, const float *fa
       st.T = 1.0f;
       return true;
     }
-    last = prim_of(av.pa[e]);
+    last = r.w;
   }
   // rounding kept every per-primitive step at or below 1: an ordinary sample
   return st.T > 1.0f - av.eps;
@@ -306,37 +348,38 @@ __device__ bool seq_sample(const AccelView &av, const void *pay, const float *fa
 // consecutive samples remain in one cell), then composited in sample order.
 // The ray's pairs are sorted by (first sample, primitive id): a window visits
 // only the pairs that overlap it, and the primitives of one sample are summed
-// in primitive-id order.
+// in primitive-id order within each group of pairs with the same first sample.
 constexpr int kWin = 12;
 
 template <bool BF16, bool FADE>
-__device__ void march_ray(const AccelView &av, const void *pay, const float *fade, uint64_t beg, uint64_t end,
-                          RayState &st) {
+__device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay, const float *fade, uint32_t seg,
+                          int n, const Dir &d, RayState &st) {
   const float dt = av.step, lim = 1.0f - av.eps;
   const int M = av.M;
   const float hM = 0.5f * (float)(M - 1);
   const size_t M3 = (size_t)M * M * M;
-  uint64_t e0 = beg;           // pairs before e0 have ended before the window
-  int J = av.pj[beg].x;
+  int e0 = 0;                  // pairs before e0 have ended before the window
+  int J = av.pr[seg].x;
   ++st.n_pj;
   while (true) {
     float as[kWin], ar[kWin], ag[kWin], ab[kWin];
-    int cnt[kWin];
+    // samples of the window inside at least one primitive, and the number of
+    // primitives containing each, 8 bits per sample (exact when the ray has
+    // at most 255 pairs; longer lists count their prim-samples afterwards)
+    uint32_t occ = 0, cp[kWin / 4] = {};
 #pragma unroll
-    for (int w = 0; w < kWin; ++w) {
-      as[w] = ar[w] = ag[w] = ab[w] = 0.f;
-      cnt[w] = 0;
-    }
+    for (int w = 0; w < kWin; ++w) as[w] = ar[w] = ag[w] = ab[w] = 0.f;
     const int J1 = J + kWin;
-    for (uint64_t e = e0; e < end; ++e) {
-      const int2 r = av.pj[e];
+    for (int i = e0; i < n; ++i) {
+      const int4 r = av.pr[seg + i];
       ++st.n_pj;
       if (r.x >= J1) break;
       if (r.y < J) continue;
       const int lo = max(r.x, J) - J, hi = min(r.y, J1 - 1) - J;
-      const float4 A = av.pa[e];
-      const float4 B = av.pb[e];
-      ++st.n_pab;
+      occ |= ((2u << hi) - 1u) & ~((1u << lo) - 1u);
+      float4 A, B;
+      fr.local(av, r.z, d, A, B);
+      if (!fr.lds) ++st.n_pab;
       const size_t kb = (size_t)prim_of(A) * M3;
       int cur = -1;
       float4 v[8];
@@ -356,54 +399,85 @@ __device__ void march_ray(const AccelView &av, const void *pay, const float *fad
             }
             cur = c.idx;
           }
-          const float4 s = trilerp(v, c);
-          as[w] += s.w;
-          ar[w] = fmaf(s.w, s.x, ar[w]);
-          ag[w] = fmaf(s.w, s.y, ag[w]);
-          ab[w] = fmaf(s.w, s.z, ab[w]);
-          ++cnt[w];
+          const float4 sv = trilerp(v, c);
+          as[w] += sv.w;
+          ar[w] = fmaf(sv.w, sv.x, ar[w]);
+          ag[w] = fmaf(sv.w, sv.y, ag[w]);
+          ab[w] = fmaf(sv.w, sv.z, ab[w]);
+          cp[w / 4] += 1u << (8 * (w % 4));
         }
       }
     }
+    // composite the occupied samples in order; a sample whose summed step
+    // saturates under the sequential combine leaves the unrolled loop and is
+    // taken primitive by primitive, then the loop resumes after it
     bool stop = false;
+    int w0 = 0;
+    while (!stop && w0 < kWin) {
+      int wseq = kWin;
 #pragma unroll
-    for (int w = 0; w < kWin; ++w) {
-      if (!stop && cnt[w] > 0) {
-        ++st.n_ray;
-        st.n_prim += cnt[w];
-        if (av.combine && st.T + as[w] * dt > 1.0f)
-          stop = seq_sample<BF16, FADE>(av, pay, fade, e0, end, J + w, st);
-        else
-          stop = composite(st, J + w, as[w], ar[w], ag[w], ab[w], dt, lim);
+      for (int w = 0; w < kWin; ++w) {
+        if (w >= w0 && !stop && wseq == kWin && ((occ >> w) & 1u)) {
+          ++st.n_ray;
+          st.n_prim += (cp[w / 4] >> (8 * (w % 4))) & 0xffu;
+          if (av.combine && st.T + as[w] * dt > 1.0f) wseq = w;
+          else stop = composite(st, J + w, as[w], ar[w], ag[w], ab[w], dt, lim);
+        }
       }
+      if (wseq < kWin) stop = seq_sample<BF16, FADE>(av, fr, pay, fade, seg, n, d, J + wseq, st);
+      w0 = wseq + 1;
     }
     if (stop) break;
     // next occupied sample: every pair in front of e0 ends before J1, and all
     // later pairs start no earlier than e0 does
-    while (e0 < end) {
+    while (e0 < n) {
       ++st.n_pj;
-      if (av.pj[e0].y >= J1) break;
+      if (av.pr[seg + e0].y >= J1) break;
       ++e0;
     }
-    if (e0 == end) break;
-    J = max(J1, av.pj[e0].x);
+    if (e0 == n) break;
+    J = max(J1, av.pr[seg + e0].x);
     ++st.n_pj;
+  }
+  if (n > 255) {   // the 8-bit per-sample counts may have wrapped: count the samples up to the last one
+    uint32_t np = 0;
+    for (int i = 0; i < n; ++i) {
+      const int4 r = av.pr[seg + i];
+      np += (uint32_t)max(0, min(r.y, st.j_end) - r.x + 1);
+    }
+    st.n_prim = np;
   }
 }
 
+// Frames of a tile's culling list staged in LDS when the list has at most
+// this many entries.
+constexpr int kFrameLds = 256;
+
 template <bool BF16, bool FADE>
-__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_march_fwd(AccelView av, const void *__restrict__ pay,
-                                                             const float *__restrict__ bg,
-                                                             float4 *__restrict__ rgba,
-                                                             mvp_ray_aux *__restrict__ aux,
-                                                             unsigned long long *__restrict__ counters) {
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_march_fwd(
+    AccelView av, const void *__restrict__ pay, const float *__restrict__ bg, float4 *__restrict__ rgba,
+    mvp_ray_aux *__restrict__ aux, unsigned long long *__restrict__ counters) {
   __shared__ int s_list[kTileThreads];
   __shared__ int s_wave[kTileThreads / kWave];
+  __shared__ float4 s_frm[4 * kFrameLds];
+  __shared__ float s_dir[3][kTileThreads];
   extern __shared__ float s_fade[];   // [M] when FADE
   const int slot = xcd_tile(blockIdx.x, av.V * av.tiles_x * av.tiles_y);
   if (slot < 0) return;
   const int tile = blocked_tile(slot, av.tiles_x, av.tiles_y);
   if (FADE) fill_fade(s_fade, av.M, av.fade_alpha, av.fade_beta);   // visible after compact_tile's barrier
+  const uint64_t lb = av.tile_off[tile], len = av.tile_off[tile + 1] - lb;
+  const bool staged = len <= (uint64_t)kFrameLds;
+  unsigned long long n_stage = 0;
+  if (staged) {   // the tile's entry frames (visible after compact_tile's barrier)
+    for (int e = threadIdx.x; e < (int)len; e += kTileThreads) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) s_frm[4 * e + r] = av.ef[3 * (lb + e) + r];
+      s_frm[4 * e + 3] = make_float4(__int_as_float((int)av.tile_list[lb + e]), 0.f, 0.f, 0.f);
+      ++n_stage;
+    }
+  }
+  const Frames fr{staged ? s_frm : nullptr, lb};
   int total;
   {
     size_t ray;
@@ -411,7 +485,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3)
     const bool valid = tile_ray(av, tile, threadIdx.x, &ray, &v, &px, &py);
     bool act = false;
     if (valid) {
-      act = av.ray_off[ray + 1] > av.ray_off[ray];
+      act = av.ray_nj[ray].x > 0;
       if (!act) {
         float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
         if (bg) o = make_float4(bg[3 * ray], bg[3 * ray + 1], bg[3 * ray + 2], 0.f);
@@ -426,7 +500,12 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3)
     size_t ray;
     int v, px, py;
     tile_ray(av, tile, s_list[threadIdx.x], &ray, &v, &px, &py);
-    march_ray<BF16, FADE>(av, pay, s_fade, av.ray_off[ray], av.ray_off[ray + 1], st);
+    float d[3];
+    pixel_ray(av.cams[v], px, py, d);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s_dir[i][threadIdx.x] = d[i];
+    march_ray<BF16, FADE>(av, fr, pay, s_fade, (uint32_t)av.ray_seg[ray], av.ray_nj[ray].x,
+                          Dir{&s_dir[0][threadIdx.x], kTileThreads}, st);
     if (bg) {   // composite over the background: I + (1 - A) B
       const float u = 1.0f - st.T;
       st.I0 = fmaf(u, bg[3 * ray], st.I0);
@@ -438,8 +517,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3)
   }
   if (counters) {
     const unsigned long long c[5] = {wave_sum_u64(st.n_ray), wave_sum_u64(st.n_prim), wave_sum_u64(st.n_cell),
-                                     wave_sum_u64(st.n_pj), wave_sum_u64(st.n_pab)};
-    if ((threadIdx.x & (kWave - 1)) == 0 && c[3]) {
+                                     wave_sum_u64(st.n_pj), wave_sum_u64(st.n_pab + n_stage)};
+    if ((threadIdx.x & (kWave - 1)) == 0 && (c[3] | c[4])) {
 #pragma unroll
       for (int i = 0; i < 5; ++i) atomicAdd(&counters[i], c[i]);
     }
@@ -516,18 +595,29 @@ __global__ __launch_bounds__(256) void k_bwd_rays(AccelView av, const void *__re
   }
   int kstar = -1;
   if (ax.j_end >= 0 && ax.t_prev >= 0.f) {
+    // the ray's pairs open at its last sample, in increasing primitive id as
+    // the forward visited them
     const float tau = (float)ax.j_end * av.step;
-    const uint64_t b = av.ray_off[r], end = av.ray_off[r + 1];
+    const int tile = slot_tile(av, r);
+    const Frames fr{nullptr, av.tile_off[tile]};
+    int v, px, py;
+    slot_pixel(av, r, &v, &px, &py);
+    float d[3];
+    pixel_ray(av.cams[v], px, py, d);
+    const uint32_t seg = (uint32_t)av.ray_seg[r];
+    const int n = av.ray_nj[r].x;
     if (av.combine) {
       float T = ax.t_prev;
       int last = -1;
-      for (uint64_t e = next_by_id(av, b, end, ax.j_end, last); e < end;
-           e = next_by_id(av, b, end, ax.j_end, last)) {
-        const float4 s = sample_pair<BF16, FADE>(av, pay, s_fade, e, tau);
+      for (int i = next_by_id(av, seg, n, ax.j_end, last); i < n; i = next_by_id(av, seg, n, ax.j_end, last)) {
+        const int4 pq = av.pr[seg + i];
+        float4 A, B;
+        fr.local(av, pq.z, Dir{d, 1}, A, B);
+        const float4 s = sample_pair<BF16, FADE>(av, pay, s_fade, A, B, tau);
         const float Tn = T + s.w * av.step;
-        last = prim_of(av.pa[e]);
+        last = pq.w;
         if (Tn > 1.0f) {
-          kstar = last;
+          kstar = prim_of(A);
           tdot = -(g.x * s.x + g.y * s.y + g.z * s.z);
           wsig = 1.0f - T;
           break;
@@ -536,11 +626,13 @@ __global__ __launch_bounds__(256) void k_bwd_rays(AccelView av, const void *__re
       }
     } else {
       float sig = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-      for (uint64_t e = b; e < end; ++e) {
-        const int2 jr = av.pj[e];
-        if (jr.x > ax.j_end) break;          // sorted by first sample
-        if (jr.y < ax.j_end) continue;
-        const float4 s = sample_pair<BF16, FADE>(av, pay, s_fade, e, tau);
+      for (int i = 0; i < n; ++i) {
+        const int4 pq = av.pr[seg + i];
+        if (pq.x > ax.j_end) break;          // sorted by first sample
+        if (pq.y < ax.j_end) continue;
+        float4 A, B;
+        fr.local(av, pq.z, Dir{d, 1}, A, B);
+        const float4 s = sample_pair<BF16, FADE>(av, pay, s_fade, A, B, tau);
         sig += s.w;
         c0 = fmaf(s.w, s.x, c0);
         c1 = fmaf(s.w, s.y, c1);
@@ -639,17 +731,22 @@ template <bool BF16, bool LDS_ACC, bool FADE, typename GAcc>
 __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__restrict__ rot,
                                          const float *__restrict__ scale, const void *__restrict__ pay,
                                          const mvp_ray_aux *__restrict__ aux, const float4 *__restrict__ grad_rgba,
-                                         const RayConst *__restrict__ rc, uint32_t e, int k, GAcc *gdst,
-                                         float fxs, const float *s_fade, bool pose, float (&P)[15],
-                                         uint32_t &runs) {
+                                         const RayConst *__restrict__ rc, const uint2 rec, uint64_t gent, int tile,
+                                         int k, GAcc *gdst, float fxs, const float *s_fade, bool pose,
+                                         float (&P)[15], uint32_t &runs) {
   const int M = av.M;
   const float hM = 0.5f * (float)(M - 1);
   const size_t M3 = (size_t)M * M * M;
   const float dt = av.step;
-  const float4 A = av.pa[e];
-  const float4 B = av.pb[e];
-  const int2 jr = av.pj[e];
-  const int ray = __float_as_int(B.w);
+  const int2 jr = make_int2((int)(rec.x & 0xffffffu), (int)rec.y);
+  size_t ray;
+  int rv, px, py;
+  (void)tile_ray(av, tile, (int)(rec.x >> 24), &ray, &rv, &px, &py);
+  float d[3];
+  pixel_ray(av.cams[rv], px, py, d);
+  float4 A, B;   // the pair's local ray, from the frame of its culling-list entry gent
+  const Frames fr{nullptr, gent};
+  fr.local(av, 0, Dir{d, 1}, A, B);
   const mvp_ray_aux ax = aux[ray];
   const float4 g = grad_rgba[ray];
   const RayConst rcv = rc[ray];
@@ -798,16 +895,7 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
   }
   if (!pose) return;
   // y = A (o + tau d - t), A = diag(1/s) R^T; d is the unit pixel ray
-  int rv, px, py;
-  slot_pixel(av, (size_t)ray, &rv, &px, &py);
   const DevCam &cam = av.cams[rv];
-  const float u = (float)px + 0.5f, wv = (float)py + 0.5f;
-  float d[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) d[i] = cam.P[3 * i] * u + cam.P[3 * i + 1] * wv + cam.P[3 * i + 2];
-  const float inv = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) d[i] *= inv;
   const float G[3] = {G0, G1, G2}, H[3] = {H0, H1, H2};
   float Am[9], t[3];
 #pragma unroll
@@ -838,18 +926,21 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
 
 
 
-// Samples the backward replays for pair e: its samples up to the ray's last.
-// Raises `bound` to the pair's bound on what it adds to any one payload
-// gradient value (see RayBound), if larger.
+// Samples the backward replays for the pair of entry record rec (of a
+// culling-list entry of `tile`): its samples up to the ray's last.  Raises
+// `bound` to the pair's bound on what it adds to any one payload gradient
+// value (see RayBound), if larger.
 // Maximum that propagates NaN (a non-finite bound must reach fixed_scale).
 __device__ __forceinline__ float nan_max(float a, float b) {
   return (a == a && b == b) ? fmaxf(a, b) : __builtin_nanf("");
 }
 
 __device__ __forceinline__ int pair_len(const AccelView &av, const mvp_ray_aux *__restrict__ aux,
-                                        const RayBound *__restrict__ rbd, uint32_t e, float &bound) {
-  const int2 jr = av.pj[e];
-  const int ray = __float_as_int(av.pb[e].w);
+                                        const RayBound *__restrict__ rbd, const uint2 rec, int tile, float &bound) {
+  const int2 jr = make_int2((int)(rec.x & 0xffffffu), (int)rec.y);
+  size_t ray;
+  int rv, px, py;
+  (void)tile_ray(av, tile, (int)(rec.x >> 24), &ray, &rv, &px, &py);
   const int je = aux[ray].j_end;
   const int n = max(0, min(jr.y, je) - jr.x + 1);
   if (n > 0) {
@@ -907,8 +998,14 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
   __shared__ uint32_t s_wcnt[2][THREADS / kWave][kLenBuckets];
   __shared__ float s_pose[THREADS / kWave][16];
   __shared__ float s_bnd[THREADS / kWave];
-  __shared__ uint64_t s_start[kItemEntries];
-  __shared__ uint32_t s_pre[kItemEntries + 1];
+  // the pairs of an item come in sub-lists, four per entry (the rays of each
+  // wave of its tile): their starts in ent_rec and their prefix sums
+  constexpr int kSub = 4 * kItemEntries;
+  __shared__ uint64_t s_start[kSub];
+  __shared__ uint32_t s_pre[kSub + 1];
+  __shared__ uint32_t s_wsum[kSub / kWave];
+  __shared__ uint64_t s_gent[kItemEntries];
+  __shared__ int s_tile[kItemEntries];
   __shared__ int s_prim;
   const int M = av.M;
   const size_t M3 = (size_t)M * M * M;
@@ -939,26 +1036,40 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
     const uint64_t chunk = it - av.item_off[k];
     const uint64_t eb = av.prim_entry_off[k] + chunk * (uint64_t)av.item_entries;
     const int nent = (int)min<uint64_t>((uint64_t)av.item_entries, av.prim_entry_off[k + 1] - eb);
-    if (wave == 0) {          // the entries' pair ranges and their prefix sums
+    const int nsub = 4 * nent;
+    uint32_t incl = 0;
+    if (threadIdx.x < kSub) {   // sub-list u = 4 q + w: entry q, wave w of its tile
+      const int u = threadIdx.x, q = u >> 2, w = u & 3;
       uint32_t cnt = 0;
-      if (lane < nent) {
-        const uint32_t g = av.prim_entries[eb + lane];
-        s_start[lane] = av.entry_off[g];
-        cnt = (uint32_t)(av.entry_off[g + 1] - av.entry_off[g]);
+      if (u < nsub) {
+        const uint32_t g = av.prim_entries[eb + q];
+        s_start[u] = av.ent_base[g] + (uint64_t)w * kWave;
+        cnt = av.ent_n[4 * (uint64_t)g + w];
+        if (w == 0) {
+          s_gent[q] = g;
+          s_tile[q] = (int)av.ent_tile[g];
+        }
       }
-      uint32_t incl = cnt;
+      incl = cnt;
 #pragma unroll
       for (int d = 1; d < kWave; d <<= 1) {
         const uint32_t o = __shfl_up(incl, d, kWave);
         if (lane >= d) incl += o;
       }
-      if (lane == 0) s_pre[0] = 0;
-      if (lane < kItemEntries) s_pre[lane + 1] = incl;
+      if (lane == kWave - 1) s_wsum[wave] = incl;
     }
     if (LDS_ACC && out.pay)
       for (int i = threadIdx.x; i < nlds; i += THREADS) s_grad[i] = (GAcc)0;
     __syncthreads();
-    const uint32_t total = s_pre[nent];
+    if (threadIdx.x < kSub) {   // prefix sums over the sub-lists
+      uint32_t base = 0;
+#pragma unroll
+      for (int w = 0; w < kSub / kWave; ++w) base += w < wave ? s_wsum[w] : 0u;
+      if (threadIdx.x == 0) s_pre[0] = 0;
+      s_pre[threadIdx.x + 1] = base + incl;
+    }
+    __syncthreads();
+    const uint32_t total = s_pre[nsub];
     GAcc *gdst = nullptr;
     if constexpr (LDS_ACC) {
       if (out.pay) gdst = s_grad;
@@ -983,7 +1094,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
       const uint32_t c0 = threadIdx.x * per, c1 = min(total, c0 + per);
       int q0 = 0;
       if (c0 < c1) {
-        int hi = nent - 1;
+        int hi = nsub - 1;
         while (q0 < hi) {
           const int mid = (q0 + hi + 1) >> 1;
           if (s_pre[mid] <= c0) q0 = mid; else hi = mid - 1;
@@ -993,7 +1104,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
       __syncthreads();
       for (uint32_t i = c0, q = q0; i < c1; ++i) {
         while (s_pre[q + 1] <= i) ++q;
-        const int n = pair_len(av, aux, rbd, av.entry_pairs[s_start[q] + (i - s_pre[q])], bound);
+        const int n = pair_len(av, aux, rbd, av.ent_rec[s_start[q] + (i - s_pre[q])], s_tile[q >> 2], bound);
         ++n_visit;
         const int b = n > 0 ? len_bucket(n) : 0xff;
         s_pcls[i] = (uint8_t)b;
@@ -1055,14 +1166,14 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
       const uint32_t live = s_live;
       for (uint32_t p = threadIdx.x; p < live; p += THREADS) {
         const uint32_t i = s_sort[p];
-        int q = 0, hi = nent - 1;    // entry of flattened pair i: last q with s_pre[q] <= i
+        int q = 0, hi = nsub - 1;    // entry of flattened pair i: last q with s_pre[q] <= i
         while (q < hi) {
           const int mid = (q + hi + 1) >> 1;
           if (s_pre[mid] <= i) q = mid; else hi = mid - 1;
         }
-        const uint32_t e = av.entry_pairs[s_start[q] + (i - s_pre[q])];
-        bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, e, k, gdst, fscale, s_fade, pose, P,
-                                      n_run);
+        const uint2 rec = av.ent_rec[s_start[q] + (i - s_pre[q])];
+        bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, rec, s_gent[q >> 2], s_tile[q >> 2], k, gdst,
+                                      fscale, s_fade, pose, P, n_run);
         ++n_rep;
       }
     } else {
@@ -1077,7 +1188,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
       const uint32_t iend = kChunkedPairs ? min(total, i0 + per) : total;
       int q0 = 0;
       if (i0 < iend) {
-        int hi = nent - 1;    // entry of flattened pair i0: last q with s_pre[q] <= i0
+        int hi = nsub - 1;    // entry of flattened pair i0: last q with s_pre[q] <= i0
         while (q0 < hi) {
           const int mid = (q0 + hi + 1) >> 1;
           if (s_pre[mid] <= i0) q0 = mid; else hi = mid - 1;
@@ -1086,7 +1197,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
       if (LDS_ACC && out.pay) {   // the item's bound, for the fixed-point scale
         for (uint32_t i = i0, q = q0; i < iend; i += stride) {
           while (s_pre[q + 1] <= i) ++q;
-          (void)pair_len(av, aux, rbd, av.entry_pairs[s_start[q] + (i - s_pre[q])], bound);
+          (void)pair_len(av, aux, rbd, av.ent_rec[s_start[q] + (i - s_pre[q])], s_tile[q >> 2], bound);
           ++n_visit;
         }
 #pragma unroll
@@ -1100,9 +1211,9 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
       }
       for (uint32_t i = i0, q = q0; i < iend; i += stride) {
         while (s_pre[q + 1] <= i) ++q;
-        const uint32_t e = av.entry_pairs[s_start[q] + (i - s_pre[q])];
-        bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, e, k, gdst, fscale, s_fade, pose, P,
-                                      n_run);
+        const uint2 rec = av.ent_rec[s_start[q] + (i - s_pre[q])];
+        bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, rec, s_gent[q >> 2], s_tile[q >> 2], k, gdst,
+                                      fscale, s_fade, pose, P, n_run);
         ++n_rep;
       }
     }
@@ -1202,7 +1313,7 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   if (e != hipSuccess || p.n_prim == 0 || n_items_max == 0) return e;
   // the planar 64-bit LDS gradient, when one workgroup's copy fits a CU
   const size_t lds = lds_plane(p.M) * 4 * sizeof(unsigned long long);
-  const size_t kStatic = 4096;   // static LDS of a 256-thread workgroup is under 4 KB (512: under 8 KB)
+  const size_t kStatic = 8192;   // static LDS of a 256-thread workgroup is under 8 KB (512: under 16 KB)
   bool in_lds = g_pay && lds + fade_shm + 2 * kStatic <= 160 * 1024;
   auto wgs_per_cu = [&](size_t grad) {
     for (int w = 3; w > 1; --w)
