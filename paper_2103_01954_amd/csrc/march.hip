@@ -678,19 +678,37 @@ struct BwdOut {
 };
 
 
-// The LDS copy of a primitive's payload gradient is planar, channel ch of voxel
-// v at ch * lds_plane(M) + v, with one word of padding per plane: lanes adding
-// the same corner and channel of different cells then spread over all 32 LDS
-// banks (the [voxel][channel] order of device memory would put them on 8).
-__host__ __device__ __forceinline__ size_t lds_plane(int M) { return (size_t)M * M * M + 1; }
+// The LDS copy of a primitive's payload gradient is planar: channel ch of
+// voxel (ix, iy, iz) at ch * plane + ix + iy * sy + iz * sz.  A wave adds one
+// channel of one corner per instruction, and the lanes working in one cell add
+// to its 8 different corners (see the mirrored lanes in bwd_pair); with 64-bit
+// words a bank pair is a word index mod 16, so the strides are padded until
+// the 8 corner offsets {0, 1} + {0, sy} + {0, sz} fall on 8 different bank
+// pairs (8^3: sy = 8, sz = 66), when the padded copy fits the LDS; otherwise
+// the copy is packed (sy = M, sz = M^2, plane = M^3 + 1).
+struct LdsMap {
+  int sy, sz, plane;
+};
 
-// Add the register-accumulated gradients of one cell to the LDS copy of the
-// primitive's gradient (LDS_ACC: planar 64-bit fixed point, value * scale
-// rounded to the nearest integer, which fits 32 bits) or straight to device memory
-// ([voxel][channel], FP32).  Register slot q holds corner q ^ m of the cell
-// (corner r = dx + 2 dy + 4 dz); `slots` selects the slots to add.  With the
-// fade window the opacity gradient of a stored voxel is the window times the
-// gradient of its windowed value.
+__host__ __device__ inline LdsMap lds_map(int M, bool padded) {
+  if (!padded) return LdsMap{M, M * M, M * M * M + 1};
+  auto distinct = [](int a, int b) {   // {0, 1, a, a + 1, b, b + 1, a + b, a + b + 1} mod 16
+    int seen = 0;
+    const int v[8] = {0, 1, a, a + 1, b, b + 1, a + b, a + b + 1};
+    for (int i = 0; i < 8; ++i) {
+      const int bit = 1 << (v[i] & 15);
+      if (seen & bit) return false;
+      seen |= bit;
+    }
+    return true;
+  };
+  int sy = M;
+  while ((sy & 15) == 0 || (sy & 15) == 1 || (sy & 15) == 15) ++sy;
+  int sz = sy * M;
+  while (!distinct(sy, sz)) ++sz;
+  return LdsMap{sy, sz, sz * M};
+}
+
 // One addend of the fixed-point accumulator: v * scale rounded to the nearest
 // integer (|v * scale| < 2^30 by the choice of scale), sign-extended to the
 // 64-bit two's complement word that the LDS atomic adds.
@@ -699,15 +717,16 @@ __device__ __forceinline__ unsigned long long fixed_addend(float v, float scale)
 }
 
 template <bool LDS_ACC, bool FADE, typename T>
-__device__ __forceinline__ void flush_cell(T *dst, size_t cell, int M, const float (&acc)[8][4],
+__device__ __forceinline__ void flush_cell(T *dst, size_t cell, int M, const LdsMap &lm, const float (&acc)[8][4],
                                            const float (&wq)[8], unsigned slots, unsigned m, float scale) {
-  const size_t MM = (size_t)M * M;
-  const size_t plane = lds_plane(M);
+  // cell: LDS slot of corner (0,0,0) (LDS_ACC) or its voxel index in device memory
+  const size_t sy = LDS_ACC ? (size_t)lm.sy : (size_t)M, sz = LDS_ACC ? (size_t)lm.sz : (size_t)M * M;
+  const size_t plane = (size_t)lm.plane;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     if (!((slots >> q) & 1u)) continue;
     const unsigned r = (unsigned)q ^ m;
-    const size_t vox = cell + (r & 1u) + ((r >> 1) & 1u) * (size_t)M + (r >> 2) * MM;
+    const size_t vox = cell + (r & 1u) + ((r >> 1) & 1u) * sy + (r >> 2) * sz;
     const float a3 = FADE ? acc[q][3] * wq[q] : acc[q][3];
     if constexpr (LDS_ACC) {
       atomicAdd(dst + vox, fixed_addend(acc[q][0], scale));
@@ -732,7 +751,7 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
                                          const float *__restrict__ scale, const void *__restrict__ pay,
                                          const mvp_ray_aux *__restrict__ aux, const float4 *__restrict__ grad_rgba,
                                          const RayConst *__restrict__ rc, const uint2 rec, uint64_t gent, int tile,
-                                         int k, GAcc *gdst, float fxs, const float *s_fade, bool pose,
+                                         int k, GAcc *gdst, const LdsMap &lm, float fxs, const float *s_fade, bool pose,
                                          float (&P)[15], uint32_t &runs) {
   const int M = av.M;
   const float hM = 0.5f * (float)(M - 1);
@@ -891,7 +910,10 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
         if (!(q & bit))
 #pragma unroll
           for (int ch = 0; ch < 4; ++ch) acc[q][ch] -= acc[q | bit][ch];
-    if (gdst) flush_cell<LDS_ACC, FADE>(gdst, cell, M, acc, wq, 0xffu, m, fxs);
+    if (gdst) {
+      const size_t fc = LDS_ACC ? (size_t)ci0 + (size_t)ci1 * lm.sy + (size_t)ci2 * lm.sz : (size_t)cell;
+      flush_cell<LDS_ACC, FADE>(gdst, fc, M, lm, acc, wq, 0xffu, m, fxs);
+    }
   }
   if (!pose) return;
   // y = A (o + tau d - t), A = diag(1/s) R^T; d is the unit pixel ray
@@ -984,7 +1006,8 @@ template <bool BF16, bool LDS_ACC, bool FADE, int WAVES, int THREADS>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_bwd_items(
     AccelView av, const float *__restrict__ rot, const float *__restrict__ scale, const void *__restrict__ pay,
     const mvp_ray_aux *__restrict__ aux, const float4 *__restrict__ grad_rgba, const RayConst *__restrict__ rc,
-    const RayBound *__restrict__ rbd, BwdOut out, uint32_t sort_cap, unsigned long long *__restrict__ counters) {
+    const RayBound *__restrict__ rbd, BwdOut out, uint32_t sort_cap, int padded,
+    unsigned long long *__restrict__ counters) {
   // loads of this thread: pairs visited by the ordering / bound pass, pairs
   // replayed, their cell runs (one voxel-corner set each), and the non-zero
   // gradient values it adds to device memory at the end of an item
@@ -1010,7 +1033,8 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
   const int M = av.M;
   const size_t M3 = (size_t)M * M * M;
   const int nacc = (int)(M3 * 4);                 // gradient values of one primitive
-  const int nlds = (int)(lds_plane(M) * 4);       // their planar LDS copy
+  const LdsMap lm = lds_map(M, padded != 0);
+  const int nlds = 4 * lm.plane;                  // their planar LDS copy
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const bool pose = out.pos || out.rot || out.scale;
   GAcc *s_grad = (GAcc *)s_dyn;
@@ -1173,7 +1197,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
         }
         const uint2 rec = av.ent_rec[s_start[q] + (i - s_pre[q])];
         bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, rec, s_gent[q >> 2], s_tile[q >> 2], k, gdst,
-                                      fscale, s_fade, pose, P, n_run);
+                                      lm, fscale, s_fade, pose, P, n_run);
         ++n_rep;
       }
     } else {
@@ -1213,7 +1237,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
         while (s_pre[q + 1] <= i) ++q;
         const uint2 rec = av.ent_rec[s_start[q] + (i - s_pre[q])];
         bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, rec, s_gent[q >> 2], s_tile[q >> 2], k, gdst,
-                                      fscale, s_fade, pose, P, n_run);
+                                      lm, fscale, s_fade, pose, P, n_run);
         ++n_rep;
       }
     }
@@ -1242,11 +1266,11 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
     }
     if (LDS_ACC && out.pay && total > 0) {
       float *dst = out.pay + M3 * 4 * (size_t)k;
-      const size_t plane = lds_plane(M);
       const bool ok = fscale > 0.0f;
       const float inv = ok ? 1.0f / fscale : __builtin_nanf("");   // exact: a power of two
       for (int i = threadIdx.x; i < nacc; i += THREADS) {   // device order: voxel i/4, channel i%4
-        const long long v = (long long)s_grad[(i & 3) * plane + (i >> 2)];
+        const int vx = i >> 2, ix = vx % M, iy = (vx / M) % M, iz = vx / (M * M);
+        const long long v = (long long)s_grad[(i & 3) * lm.plane + ix + iy * lm.sy + iz * lm.sz];
         if (v != 0 || !ok) {
           unsafeAtomicAdd(dst + i, (float)v * inv);
           ++n_nz;
@@ -1311,9 +1335,12 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
 #undef MVP_RAYS
   e = hipGetLastError();
   if (e != hipSuccess || p.n_prim == 0 || n_items_max == 0) return e;
-  // the planar 64-bit LDS gradient, when one workgroup's copy fits a CU
-  const size_t lds = lds_plane(p.M) * 4 * sizeof(unsigned long long);
+  // the planar 64-bit LDS gradient, when one workgroup's copy fits a CU; its
+  // padded layout unless only the packed one fits
   const size_t kStatic = 8192;   // static LDS of a 256-thread workgroup is under 8 KB (512: under 16 KB)
+  auto lds_bytes = [&](bool pad) { return (size_t)lds_map(p.M, pad).plane * 4 * sizeof(unsigned long long); };
+  const int padded = lds_bytes(true) + fade_shm + 2 * kStatic <= 160 * 1024 ? 1 : 0;
+  const size_t lds = lds_bytes(padded != 0);
   bool in_lds = g_pay && lds + fade_shm + 2 * kStatic <= 160 * 1024;
   auto wgs_per_cu = [&](size_t grad) {
     for (int w = 3; w > 1; --w)
@@ -1360,15 +1387,15 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
     if (w3)                                                                                                     \
       hipLaunchKernelGGL((k_bwd_items<B, L, F, 3, kTileThreads>), dim3(grid), dim3(kTileThreads), shm, s, av,   \
                          p.rot, p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, rbd, out, sort_cap,     \
-                         counters);                                                                             \
+                         padded, counters);                                                                             \
     else if (wide_wg)                                                                                           \
       hipLaunchKernelGGL((k_bwd_items<B, L, F, 1, 2 * kTileThreads>), dim3(grid), dim3(2 * kTileThreads), shm, \
                          s, av, p.rot, p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, rbd, out,        \
-                         sort_cap, counters);                                                                   \
+                         sort_cap, padded, counters);                                                                   \
     else                                                                                                        \
       hipLaunchKernelGGL((k_bwd_items<B, L, F, 1, kTileThreads>), dim3(grid), dim3(kTileThreads), shm, s, av,   \
                          p.rot, p.scale, p.payload, aux, (const float4 *)grad_rgba, rc, rbd, out, sort_cap,     \
-                         counters);                                                                             \
+                         padded, counters);                                                                             \
   } while (0)
 #define MVP_BWD_F(B, F)                                  \
   do {                                                   \
