@@ -644,7 +644,7 @@ __global__ __launch_bounds__(kTileThreads) void k_pairs(AccelView av, float4 *__
   const uint64_t lb = av.tile_off[tile], le = av.tile_off[tile + 1];
   const uint64_t len = le - lb;
   const uint64_t rays = av.tile_rays ? av.tile_ray_off[tile + 1] - av.tile_ray_off[tile] : (uint64_t)kTileThreads;
-  const uint64_t seg = av.pair_base[tile] + (uint64_t)t * len;
+  const uint64_t seg = av.pair_base[tile] + (uint64_t)t;   // pair q at seg + q * rays
   const unsigned long long lt = (1ull << lane) - 1ull;
   int nw = 0;         // pairs written to device memory, in order
   int nt = 0;         // pairs in the sorted register tail, all after the written ones
@@ -676,20 +676,20 @@ __global__ __launch_bounds__(kTileThreads) void k_pairs(AccelView av, float4 *__
           // before every written pair still after it: those move up by one
           int at = nw;
           while (at > 0) {
-            const int4 p = pr[seg + at - 1];
+            const int4 p = pr[seg + (uint64_t)(at - 1) * rays];
             if (!pair_before(rec, p)) break;
-            pr[seg + at] = p;
+            pr[seg + (uint64_t)at * rays] = p;
             --at;
           }
-          pr[seg + at] = rec;
+          pr[seg + (uint64_t)at * rays] = rec;
           ++nw;
         } else if (nt == kTail && pair_before(rec, tb[0])) {   // after the written pairs, before the tail
-          pr[seg + nw] = rec;
+          pr[seg + (uint64_t)nw * rays] = rec;
           wl = rec;
           ++nw;
         } else {
           if (nt == kTail) {   // the tail is full: its first pair is final among the written ones
-            pr[seg + nw] = tb[0];
+            pr[seg + (uint64_t)nw * rays] = tb[0];
             wl = tb[0];
             ++nw;
 #pragma unroll
@@ -716,7 +716,7 @@ __global__ __launch_bounds__(kTileThreads) void k_pairs(AccelView av, float4 *__
   }
 #pragma unroll
   for (int q = 0; q < kTail; ++q)
-    if (q < nt) pr[seg + nw + q] = tb[q];
+    if (q < nt) pr[seg + (uint64_t)(nw + q) * rays] = tb[q];
   const int i = nw + nt;
   if (valid) {
     ray_seg[ray] = seg;

@@ -37,11 +37,12 @@ struct DevCam {
 // b = A_k d.
 // Pairs: tile t reserves len(t) * R_t pair slots from pair_base[t] (len: its
 // culling-list length; R_t: 256 for full frames, its number of rays for a ray
-// subset), ray number i of the tile the len(t) slots from pair_base[t] +
-// i * len(t).  Ray slot r owns pr[ray_seg[r] .. ray_seg[r] + ray_nj[r].x),
-// its pairs sorted by first sample and then primitive id; pair p is pr[p] =
-// (jlo, jhi, position in the tile's culling list, primitive id), and
-// ray_nj[r].y is the ray's first sample (INT_MAX if none).  The same pairs by culling-list entry, for the backward: entry g at
+// subset), pair q of ray number i of the tile at pair_base[t] + q * R_t + i
+// (so that the lanes of a wave reading or writing the q-th pairs of their
+// rays touch neighbouring slots).  Ray slot r has ray_nj[r].x pairs, the q-th
+// at pr[ray_seg[r] + q * R_t], sorted by first sample and then primitive id;
+// pair p is pr[p] = (jlo, jhi, position in the tile's culling list, primitive
+// id), and ray_nj[r].y is the ray's first sample (INT_MAX if none).  The same pairs by culling-list entry, for the backward: entry g at
 // position e of tile t = ent_tile[g] lists the pairs formed with it (at most
 // one per ray of the tile), in ray order, from ent_base[g] = pair_base[t] +
 // e * R_t: the rays of wave w of the tile (ray numbers 64w .. 64w + 63) at
@@ -202,6 +203,12 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
   return v;
+}
+
+// Number of ray slots of a tile: 256 for full frames (rays outside the image
+// included), its sampled rays for a ray subset.
+__device__ __forceinline__ int tile_ray_count(const AccelView &av, int tile) {
+  return av.tile_rays ? (int)(av.tile_ray_off[tile + 1] - av.tile_ray_off[tile]) : kTileThreads;
 }
 
 // Pixel of a ray slot.

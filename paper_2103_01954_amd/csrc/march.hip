@@ -292,10 +292,10 @@ __device__ __forceinline__ bool composite(RayState &st, int j, float sig, float 
 
 // Among the ray's pairs [0, n) (sorted by first sample) that contain sample
 // j, the one with the smallest primitive id above `after`; n if none.
-__device__ __forceinline__ int next_by_id(const AccelView &av, uint32_t seg, int n, int j, int after) {
+__device__ __forceinline__ int next_by_id(const AccelView &av, uint32_t seg, int stride, int n, int j, int after) {
   int best = INT_MAX, bi = n;
   for (int i = 0; i < n; ++i) {
-    const int4 r = av.pr[seg + i];
+    const int4 r = av.pr[seg + i * stride];
     if (r.x > j) break;
     if (r.y < j) continue;
     if (r.w > after && r.w < best) {
@@ -311,14 +311,14 @@ __device__ __forceinline__ int next_by_id(const AccelView &av, uint32_t seg, int
 // Returns true to stop.
 template <bool BF16, bool FADE>
 __device__ bool seq_sample(const AccelView &av, const Frames &fr, const void *pay, const float *fade, uint32_t seg,
-                           int n, const Dir &d, int j, RayState &st) {
+                           int stride, int n, const Dir &d, int j, RayState &st) {
   const float dt = av.step;
   const float tau = (float)j * dt;
   const float T0 = st.T;
   st.j_end = j;
   int last = -1;
-  for (int i = next_by_id(av, seg, n, j, last); i < n; i = next_by_id(av, seg, n, j, last)) {
-    const int4 r = av.pr[seg + i];
+  for (int i = next_by_id(av, seg, stride, n, j, last); i < n; i = next_by_id(av, seg, stride, n, j, last)) {
+    const int4 r = av.pr[seg + i * stride];
     float4 A, B;
     fr.local(av, r.z, d, A, B);
     const float4 s = sample_pair<BF16, FADE>(av, pay, fade, A, B, tau);
@@ -353,7 +353,7 @@ constexpr int kWin = 12;
 
 template <bool BF16, bool FADE>
 __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay, const float *fade, uint32_t seg,
-                          int n, const Dir &d, RayState &st) {
+                          int stride, int n, const Dir &d, RayState &st) {
   const float dt = av.step, lim = 1.0f - av.eps;
   const int M = av.M;
   const float hM = 0.5f * (float)(M - 1);
@@ -371,7 +371,7 @@ __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay
     for (int w = 0; w < kWin; ++w) as[w] = ar[w] = ag[w] = ab[w] = 0.f;
     const int J1 = J + kWin;
     for (int i = e0; i < n; ++i) {
-      const int4 r = av.pr[seg + i];
+      const int4 r = av.pr[seg + i * stride];
       ++st.n_pj;
       if (r.x >= J1) break;
       if (r.y < J) continue;
@@ -424,7 +424,7 @@ __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay
           else stop = composite(st, J + w, as[w], ar[w], ag[w], ab[w], dt, lim);
         }
       }
-      if (wseq < kWin) stop = seq_sample<BF16, FADE>(av, fr, pay, fade, seg, n, d, J + wseq, st);
+      if (wseq < kWin) stop = seq_sample<BF16, FADE>(av, fr, pay, fade, seg, stride, n, d, J + wseq, st);
       w0 = wseq + 1;
     }
     if (stop) break;
@@ -432,17 +432,17 @@ __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay
     // later pairs start no earlier than e0 does
     while (e0 < n) {
       ++st.n_pj;
-      if (av.pr[seg + e0].y >= J1) break;
+      if (av.pr[seg + e0 * stride].y >= J1) break;
       ++e0;
     }
     if (e0 == n) break;
-    J = max(J1, av.pr[seg + e0].x);
+    J = max(J1, av.pr[seg + e0 * stride].x);
     ++st.n_pj;
   }
   if (n > 255) {   // the 8-bit per-sample counts may have wrapped: count the samples up to the last one
     uint32_t np = 0;
     for (int i = 0; i < n; ++i) {
-      const int4 r = av.pr[seg + i];
+      const int4 r = av.pr[seg + i * stride];
       np += (uint32_t)max(0, min(r.y, st.j_end) - r.x + 1);
     }
     st.n_prim = np;
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3)
     pixel_ray(av.cams[v], px, py, d);
 #pragma unroll
     for (int i = 0; i < 3; ++i) s_dir[i][threadIdx.x] = d[i];
-    march_ray<BF16, FADE>(av, fr, pay, s_fade, (uint32_t)av.ray_seg[ray], av.ray_nj[ray].x,
+    march_ray<BF16, FADE>(av, fr, pay, s_fade, (uint32_t)av.ray_seg[ray], tile_ray_count(av, tile), av.ray_nj[ray].x,
                           Dir{&s_dir[0][threadIdx.x], kTileThreads}, st);
     if (bg) {   // composite over the background: I + (1 - A) B
       const float u = 1.0f - st.T;
@@ -605,12 +605,13 @@ __global__ __launch_bounds__(256) void k_bwd_rays(AccelView av, const void *__re
     float d[3];
     pixel_ray(av.cams[v], px, py, d);
     const uint32_t seg = (uint32_t)av.ray_seg[r];
+    const int stride = tile_ray_count(av, tile);
     const int n = av.ray_nj[r].x;
     if (av.combine) {
       float T = ax.t_prev;
       int last = -1;
-      for (int i = next_by_id(av, seg, n, ax.j_end, last); i < n; i = next_by_id(av, seg, n, ax.j_end, last)) {
-        const int4 pq = av.pr[seg + i];
+      for (int i = next_by_id(av, seg, stride, n, ax.j_end, last); i < n; i = next_by_id(av, seg, stride, n, ax.j_end, last)) {
+        const int4 pq = av.pr[seg + i * stride];
         float4 A, B;
         fr.local(av, pq.z, Dir{d, 1}, A, B);
         const float4 s = sample_pair<BF16, FADE>(av, pay, s_fade, A, B, tau);
@@ -627,7 +628,7 @@ __global__ __launch_bounds__(256) void k_bwd_rays(AccelView av, const void *__re
     } else {
       float sig = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
       for (int i = 0; i < n; ++i) {
-        const int4 pq = av.pr[seg + i];
+        const int4 pq = av.pr[seg + i * stride];
         if (pq.x > ax.j_end) break;          // sorted by first sample
         if (pq.y < ax.j_end) continue;
         float4 A, B;
