@@ -262,7 +262,13 @@ def kernel_report(m, dtype, rays, backward):
 # rocprofv3 counter passes (child processes on this GPU)
 # ----------------------------------------------------------------------------
 
-COUNTER_PASSES = [("l2", ["TCC_HIT_sum", "TCC_MISS_sum"]), ("fetch", ["FETCH_SIZE"]), ("write", ["WRITE_SIZE"])]
+# one rocprofv3 pass each (at most 4 TCC counters per pass): L2 hits and misses
+# with the requests the L2 sends towards DRAM (in 32-byte units); the L2's
+# read requests by size; and the derived FETCH_SIZE and WRITE_SIZE
+COUNTER_PASSES = [("l2", ["TCC_HIT_sum", "TCC_MISS_sum", "TCC_EA0_RDREQ_DRAM_32B_sum",
+                          "TCC_EA0_WRREQ_WRITE_DRAM_32B_sum"]),
+                  ("rdsize", ["TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum"]),
+                  ("fetch", ["FETCH_SIZE"]), ("write", ["WRITE_SIZE"])]
 
 
 def _rocprof():
@@ -313,14 +319,24 @@ def counter_passes(child_args, timeout_s=150):
 
 
 def traffic_report(pmc, copy_bytes, kern_ms):
-    """L2 hit rate and L2-to-fabric bytes (FETCH_SIZE / WRITE_SIZE in KiB per
-    dispatch, each scaled by what the counter reads for a plain device copy of
-    known size) per march kernel."""
+    """Per march kernel and per launch, from the L2's side:
+    * l2_hit_rate: TCC_HIT / (TCC_HIT + TCC_MISS);
+    * l2_read_bytes: what the L2 reads beyond itself (MALL/Infinity Cache or
+      HBM), from its read requests by size (32, 64 and 128 B);
+    * l2_write_bytes: WRITE_SIZE (its write requests, 32 or 64 B);
+    * dram_bytes: read and write requests the L2 directs at DRAM, in 32-byte
+      units (TCC_EA0_RDREQ_DRAM_32B, TCC_EA0_WRREQ_WRITE_DRAM_32B);
+    * fetch_size_ratio: FETCH_SIZE over l2_read_bytes.  FETCH_SIZE counts a
+      128-byte request as 64 bytes, which is why a plain copy of known size
+      reads as half its bytes in it (copy_fetch_ratio)."""
+    out = {}
     copy = pmc.get("copy", {})
-    f_scale = copy_bytes / (copy["FETCH_SIZE"] * 1024) if copy.get("FETCH_SIZE") else None
-    w_scale = copy_bytes / (copy["WRITE_SIZE"] * 1024) if copy.get("WRITE_SIZE") else None
-    out = {"fetch_scale": round(f_scale, 4) if f_scale else None,
-           "write_scale": round(w_scale, 4) if w_scale else None}
+    rb = lambda d: 32 * d.get("TCC_EA0_RDREQ_32B_sum", 0) + 64 * d.get("TCC_EA0_RDREQ_64B_sum", 0) + \
+        128 * d.get("TCC_EA0_RDREQ_128B_sum", 0)
+    if copy.get("FETCH_SIZE"):
+        out["copy_fetch_ratio"] = round(copy["FETCH_SIZE"] * 1024 / copy_bytes, 4)
+        if rb(copy):
+            out["copy_read_bytes_ratio"] = round(rb(copy) / copy_bytes, 4)
     for k in (KERN_FWD, KERN_BWD):
         d = pmc.get(k)
         if not d:
@@ -328,11 +344,21 @@ def traffic_report(pmc, copy_bytes, kern_ms):
         e = {}
         if "TCC_HIT_sum" in d and "TCC_MISS_sum" in d:
             e["l2_hit_rate"] = round(d["TCC_HIT_sum"] / max(d["TCC_HIT_sum"] + d["TCC_MISS_sum"], 1.0), 4)
-        if f_scale and w_scale and "FETCH_SIZE" in d and "WRITE_SIZE" in d:
-            b = d["FETCH_SIZE"] * 1024 * f_scale + d["WRITE_SIZE"] * 1024 * w_scale
-            e["l2_fabric_bytes"] = int(b)
+        r = rb(d)
+        if r:
+            e["l2_read_bytes"] = int(r)
+            if d.get("FETCH_SIZE"):
+                e["fetch_size_ratio"] = round(d["FETCH_SIZE"] * 1024 / r, 4)
+        if "WRITE_SIZE" in d:
+            e["l2_write_bytes"] = int(d["WRITE_SIZE"] * 1024)
+        if "TCC_EA0_RDREQ_DRAM_32B_sum" in d:
+            e["dram_bytes"] = int(32 * (d["TCC_EA0_RDREQ_DRAM_32B_sum"] + d.get("TCC_EA0_WRREQ_WRITE_DRAM_32B_sum", 0)))
+        if r and "WRITE_SIZE" in d:
+            e["l2_fabric_bytes"] = int(r + d["WRITE_SIZE"] * 1024)
             if kern_ms.get(k):
-                e["l2_fabric_gbs"] = round(b / (kern_ms[k] / 1e3) / 1e9, 1)
+                e["l2_fabric_gbs"] = round(e["l2_fabric_bytes"] / (kern_ms[k] / 1e3) / 1e9, 1)
+        if "dram_bytes" in e and kern_ms.get(k):
+            e["dram_gbs"] = round(e["dram_bytes"] / (kern_ms[k] / 1e3) / 1e9, 1)
         out[k] = e
     return out
 
@@ -409,10 +435,11 @@ def main():
             "bytes_moved_per_launch": k["bytes"],
             "what": "bytes the kernel's own loads and stores move (its load counts x their sizes) per launch "
                     "/ its average launch time (HIP events on its stream), against the 8 TB/s HBM peak; "
-                    "traffic = L2-to-fabric bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by "
-                    "a plain 1 GiB copy; includes Infinity Cache hits)",
+                    "traffic = bytes per launch beyond the L2 (read requests by size + WRITE_SIZE; they include "
+                    "Infinity Cache hits); dram_* = the L2's requests directed at DRAM (32-byte units)",
             "kernels": kr, "counters": traffic, "counters_error": pmc_err,
             "l2_hit_rate": t_k.get("l2_hit_rate"), "l2_fabric_gbs": t_k.get("l2_fabric_gbs"),
+            "dram_bytes": t_k.get("dram_bytes"), "dram_gbs": t_k.get("dram_gbs"),
             # the method's gather model (8 corners per prim-sample) over the whole step
             "gather_model_step_frac": round(prim_s / (ms / 1e3) * (BYTES_FWD[dtype] + BYTES_BWD[dtype]) /
                                             (HBM_PEAK_GBS * 1e9), 4),
