@@ -48,6 +48,35 @@ static size_t round_size(size_t b) {
   return (b + q - 1) / q * q;
 }
 
+PinnedPool::~PinnedPool() {
+  for (void *p : all_) (void)hipHostFree(p);
+}
+
+void *PinnedPool::get() {
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    if (!free_.empty()) {
+      void *p = free_.back();
+      free_.pop_back();
+      return p;
+    }
+  }
+  void *p = nullptr;
+  if (hipHostMalloc(&p, kPinnedBlock, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(mu_);
+  all_.push_back(p);
+  return p;
+}
+
+void PinnedPool::put(void *p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(mu_);
+  free_.push_back(p);
+}
+
 Arena::~Arena() {
   std::lock_guard<std::mutex> g(mu_);
   for (auto &p : pending_) {
@@ -314,7 +343,25 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   MVP_CHECK(temp.get(&tile_cnt, ntile));
   MVP_CHECK(temp.get(&cap, ntile));
   MVP_CHECK(temp.get(&scratch, sb));
-  MVP_HIP(hipMemcpyAsync(a->cams, a->cams_host.data(), n_views * sizeof(DevCam), hipMemcpyHostToDevice, s));
+  // cameras up and list sizes down through a pinned block (returned once the
+  // build has synchronised, or on any early return)
+  struct PinHold {
+    PinnedPool &pool;
+    void *p;
+    hipStream_t s;
+    bool synced = false;
+    ~PinHold() {   // a copy still in flight on an early return must not see the block reused
+      if (p && !synced) (void)hipStreamSynchronize(s);
+      pool.put(p);
+    }
+  } pin{ctx->pinned, ctx->pinned.get(), s};
+  const size_t cam_bytes = n_views * sizeof(DevCam);
+  if (pin.p && cam_bytes + 64 <= kPinnedBlock) {
+    memcpy((char *)pin.p + 64, a->cams_host.data(), cam_bytes);
+    MVP_HIP(hipMemcpyAsync(a->cams, (char *)pin.p + 64, cam_bytes, hipMemcpyHostToDevice, s));
+  } else {
+    MVP_HIP(hipMemcpyAsync(a->cams, a->cams_host.data(), cam_bytes, hipMemcpyHostToDevice, s));
+  }
   MVP_HIP(launch_zero_u64((uint64_t *)a->counters, kNumCounters, s));
   uint32_t *flag = nullptr;
   if (rays) {
@@ -347,13 +394,16 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   MVP_HIP(launch_scan_u32_u64(tile_cnt, a->tile_off, ntile, scratch, s));
   MVP_HIP(launch_tile_capacity(tile_cnt, rcnt, ntile, cap, s));
   MVP_HIP(launch_scan_u32_u64(cap, a->pair_base, ntile, scratch, s));
-  uint64_t sizes[2] = {0, 0};
-  uint32_t flag_h = 0;
-  if (flag) MVP_HIP(hipMemcpyAsync(&flag_h, flag, sizeof flag_h, hipMemcpyDeviceToHost, s));
-  MVP_HIP(hipMemcpyAsync(&sizes[0], a->tile_off + ntile, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  MVP_HIP(hipMemcpyAsync(&sizes[1], a->pair_base + ntile, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  // the three sizes gathered into one small device block, then one copy down
+  uint64_t *dsz = (uint64_t *)a->counters + kCntSizes;
+  MVP_HIP(launch_gather_sizes(a->tile_off + ntile, a->pair_base + ntile, flag, dsz, s));
+  uint64_t host_sz[3] = {0, 0, 0};
+  uint64_t *hsz = pin.p ? (uint64_t *)pin.p : host_sz;
+  MVP_HIP(hipMemcpyAsync(hsz, dsz, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   MVP_HIP(hipStreamSynchronize(s));
-  const uint64_t n_tile_pairs = sizes[0], capacity = sizes[1];
+  pin.synced = true;
+  const uint64_t n_tile_pairs = hsz[0], capacity = hsz[1];
+  const uint32_t flag_h = (uint32_t)hsz[2];
   if (flag_h & 1u) { set_error("a ray pixel id is outside [0, n_views*height*width)"); return MVP_ERR_INVALID; }
   if (flag_h & 2u) { set_error("more than 256 rays in one 16x16 tile (repeated pixel ids)"); return MVP_ERR_INVALID; }
   if (capacity >= (uint64_t)1 << 32) {

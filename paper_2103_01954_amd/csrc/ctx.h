@@ -47,6 +47,21 @@ class Arena {
   size_t held_ = 0;
 };
 
+// Small pinned host blocks for the build's transfers (cameras up, list sizes
+// down), so that they are direct DMA copies rather than copies staged through
+// the runtime's own buffers.  Blocks are kPinnedBlock bytes, allocated on
+// first use and kept until the context is destroyed.
+constexpr size_t kPinnedBlock = 64 * 1024;
+class PinnedPool {
+ public:
+  ~PinnedPool();
+  void *get();            // nullptr if pinned memory cannot be allocated
+  void put(void *p);
+ private:
+  std::mutex mu_;
+  std::vector<void *> free_, all_;
+};
+
 class Server;  // serving scheduler (serve.cpp)
 
 }  // namespace mvp
@@ -64,6 +79,7 @@ struct KernelTimer {
 struct mvp_ctx {
   int device = 0;
   mvp::Arena arena;
+  mvp::PinnedPool pinned;
   mvp::KernelTimer timer;
   std::atomic<int> live_accels{0};
   mvp::Server *server = nullptr;

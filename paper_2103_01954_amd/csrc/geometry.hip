@@ -588,6 +588,21 @@ __device__ inline bool pair_of(const Staged &sm, int e, const float d[3], float 
 }
 
 
+__global__ void k_gather_sizes(const uint64_t *__restrict__ n_entries, const uint64_t *__restrict__ capacity,
+                               const uint32_t *__restrict__ flag, uint64_t *__restrict__ out) {
+  if (threadIdx.x == 0) {
+    out[0] = *n_entries;
+    out[1] = *capacity;
+    out[2] = flag ? (uint64_t)*flag : 0ull;
+  }
+}
+
+hipError_t launch_gather_sizes(const uint64_t *n_entries, const uint64_t *capacity, const uint32_t *flag,
+                               uint64_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_sizes, dim3(1), dim3(64), 0, s, n_entries, capacity, flag, out);
+  return hipGetLastError();
+}
+
 // Pair capacity of every tile: its culling-list length times its rays.
 __global__ __launch_bounds__(256) void k_tile_capacity(const uint32_t *__restrict__ tile_cnt,
                                                        const uint32_t *__restrict__ tile_rays_cnt, size_t ntile,

@@ -234,7 +234,8 @@ enum : int {
   kCntBwdRuns = 7,      // backward: cell runs (voxel-corner sets loaded)
   kCntBwdFlush = 8,     // backward: non-zero gradient values added to device memory
   kCntPairs = 9,        // build: (ray, primitive) pairs with at least one sample
-  kNumCounters = 10
+  kCntSizes = 10,       // build: culling-list entries, pair capacity, ray-subset flags (3 words)
+  kNumCounters = 13
 };
 
 // ---- launchers (return the first HIP error) --------------------------------
@@ -266,6 +267,9 @@ hipError_t launch_segment_sort(const uint64_t *off, uint32_t *data, int64_t n_se
 // range, 2 = more than 256 rays in a tile), then list them per tile
 hipError_t launch_ray_bin(const AccelView &av, uint32_t *tile_cnt, uint32_t *flag, hipStream_t s);
 hipError_t launch_ray_fill(const AccelView &av, uint32_t *cursor, uint32_t *tile_rays, hipStream_t s);
+// out[0] = *n_entries, out[1] = *capacity, out[2] = *flag (0 if flag is null)
+hipError_t launch_gather_sizes(const uint64_t *n_entries, const uint64_t *capacity, const uint32_t *flag,
+                               uint64_t *out, hipStream_t s);
 // pair capacity of every tile: culling-list length (tile_cnt) times its rays
 // (256, or tile_rays_cnt for a ray subset)
 hipError_t launch_tile_capacity(const uint32_t *tile_cnt, const uint32_t *tile_rays_cnt, size_t ntile, uint32_t *cap,
