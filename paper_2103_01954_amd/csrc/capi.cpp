@@ -268,7 +268,7 @@ static mvp_status read_u64(const uint64_t *dev, uint64_t *host, hipStream_t s) {
 
 mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams, int32_t n_views,
                        const mvp_march_params *params, const int64_t *rays, int64_t n_rays,
-                       mvp_accel **out, hipStream_t s, const Admit *admit) {
+                       mvp_accel **out, hipStream_t s, const Admit *admit, bool for_backward) {
   if (!ctx || !out || !cams) { set_error("NULL argument"); return MVP_ERR_INVALID; }
   *out = nullptr;
   MVP_CHECK(check_prims(prims, false));
@@ -413,37 +413,72 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   }
   const size_t ntp = n_tile_pairs ? n_tile_pairs : 1;
   const size_t npc = capacity ? capacity : 1;
-  if (admit)
-    MVP_CHECK(admit->fn(admit->user, ntp * (4 + 4 + 48 + 8 + 16 + 4) + (size_t)N * 20 + 24 + npc * 24 + 8 * 256));
+  const size_t list_bytes = for_backward ? ntp * (4 + 4 + 48 + 8 + 16 + 4) + (size_t)N * 20 + 24 + npc * 24
+                                         : ntp * (4 + 48) + npc * 16;
+  if (admit) MVP_CHECK(admit->fn(admit->user, list_bytes + 8 * 256));
+  a->for_backward = for_backward;
   MVP_CHECK(keep.get(&a->tile_list, ntp));
-  MVP_CHECK(keep.get(&a->prim_entries, ntp));
-  MVP_CHECK(keep.get(&a->prim_entry_off, (size_t)N + 1));
-  MVP_CHECK(keep.get(&a->item_off, (size_t)N + 1));
   MVP_CHECK(keep.get(&a->ef, 3 * ntp));
-  MVP_CHECK(keep.get(&a->ent_base, ntp));
-  MVP_CHECK(keep.get(&a->ent_n, 4 * ntp));
-  MVP_CHECK(keep.get(&a->ent_tile, ntp));
   MVP_CHECK(keep.get(&a->pr, npc));
-  MVP_CHECK(keep.get(&a->ent_rec, npc));
   uint32_t *prim_cnt = nullptr;
-  MVP_CHECK(temp.get(&prim_cnt, (size_t)N + 1));
+  if (for_backward) {
+    MVP_CHECK(keep.get(&a->prim_entries, ntp));
+    MVP_CHECK(keep.get(&a->prim_entry_off, (size_t)N + 1));
+    MVP_CHECK(keep.get(&a->item_off, (size_t)N + 1));
+    MVP_CHECK(keep.get(&a->ent_base, ntp));
+    MVP_CHECK(keep.get(&a->ent_n, 4 * ntp));
+    MVP_CHECK(keep.get(&a->ent_tile, ntp));
+    MVP_CHECK(keep.get(&a->ent_rec, npc));
+    MVP_CHECK(temp.get(&prim_cnt, (size_t)N + 1));
+  }
   av = a->view(2);
   MVP_HIP(launch_zero_u32(tile_cnt, ntile, s));
   MVP_HIP(launch_tile_fill(av, rect, tile_cnt, a->tile_list, s));
   MVP_HIP(launch_segment_sort(a->tile_off, a->tile_list, (int64_t)ntile, depth, N, tx * ty, s));
-  // transposed lists (primitive -> its entries) and backward work items
-  MVP_HIP(launch_zero_u32(prim_cnt, (size_t)N, s));
-  MVP_HIP(launch_prim_entry_count(a->tile_list, n_tile_pairs, prim_cnt, s));
-  MVP_HIP(launch_scan_u32_u64(prim_cnt, a->prim_entry_off, (size_t)N, scratch, s));
-  MVP_HIP(launch_prim_entry_place(av, rect, n_tile_pairs, a->prim_entry_off, a->prim_entries, s));
   a->item_entries = backward_item_entries(prims->M);
-  MVP_HIP(launch_item_count(a->prim_entry_off, N, a->item_entries, prim_cnt, s));
-  MVP_HIP(launch_scan_u32_u64(prim_cnt, a->item_off, (size_t)N, scratch, s));
-  a->n_items_max = (int64_t)(n_tile_pairs / a->item_entries) + N;
-
-  // every ray's pairs, the entry frames and the per-entry pair lists
-  MVP_HIP(launch_pairs(av, a->ef, a->pr, a->ray_seg, a->ray_nj, a->ent_base, a->ent_n, a->ent_tile, a->ent_rec,
-                       a->counters + kCntPairs, s));
+  a->n_items_max = for_backward ? (int64_t)(n_tile_pairs / a->item_entries) + N : 0;
+  if (!for_backward) {
+    MVP_HIP(launch_pairs(av, a->ef, a->pr, a->ray_seg, a->ray_nj, nullptr, nullptr, nullptr, nullptr,
+                         a->counters + kCntPairs, s));
+  } else {
+    // The transposed lists (primitive -> its entries) and the backward work
+    // items need only the sorted culling lists: they run on the context's side
+    // stream while the pairs kernel (every ray's pairs, the entry frames and the
+    // per-entry pair lists) runs on the build's stream, which then waits for
+    // them, so everything enqueued after the build (and the recycling of the
+    // temporaries) follows both.
+    struct Events {
+      hipEvent_t fork = nullptr, join = nullptr;
+      ~Events() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+      }
+    } ev;
+    MVP_HIP(hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming));
+    MVP_HIP(hipEventCreateWithFlags(&ev.join, hipEventDisableTiming));
+    MVP_HIP(hipEventRecord(ev.fork, s));
+    MVP_HIP(hipStreamWaitEvent(ctx->side, ev.fork, 0));
+    hipError_t te = hipSuccess;
+    {
+      hipStream_t s2 = ctx->side;
+      auto run = [&](hipError_t e) { if (te == hipSuccess) te = e; };
+      run(launch_zero_u32(prim_cnt, (size_t)N, s2));
+      if (te == hipSuccess) run(launch_prim_entry_count(a->tile_list, n_tile_pairs, prim_cnt, s2));
+      if (te == hipSuccess) run(launch_scan_u32_u64(prim_cnt, a->prim_entry_off, (size_t)N, scratch, s2));
+      if (te == hipSuccess)
+        run(launch_prim_entry_place(av, rect, n_tile_pairs, a->prim_entry_off, a->prim_entries, s2));
+      if (te == hipSuccess) run(launch_item_count(a->prim_entry_off, N, a->item_entries, prim_cnt, s2));
+      if (te == hipSuccess) run(launch_scan_u32_u64(prim_cnt, a->item_off, (size_t)N, scratch, s2));
+    }
+    const hipError_t pe = launch_pairs(av, a->ef, a->pr, a->ray_seg, a->ray_nj, a->ent_base, a->ent_n, a->ent_tile,
+                                       a->ent_rec, a->counters + kCntPairs, s);
+    hipError_t je = hipEventRecord(ev.join, ctx->side);
+    if (je == hipSuccess) je = hipStreamWaitEvent(s, ev.join, 0);
+    if (je != hipSuccess) (void)hipStreamSynchronize(ctx->side);   // no temporary may be recycled under it
+    MVP_HIP(je);
+    MVP_HIP(te);
+    MVP_HIP(pe);
+  }
   MVP_HIP(hipEventCreateWithFlags(&a->built, hipEventDisableTiming));
   MVP_HIP(hipEventRecord(a->built, s));
 
@@ -451,7 +486,9 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   a->n_ray_pairs = -1;   // read from the device on demand (mvp_accel_get_info)
   a->pair_capacity = capacity;
   a->bytes = (int64_t)(n_views * sizeof(DevCam) + 3 * (size_t)N * 16 + 2 * (ntile + 1) * 8 + R * 16 +
-                       kNumCounters * 8 + n_tile_pairs * (4 + 4 + 48 + 8 + 16 + 4) + (size_t)N * 24 + capacity * 24 +
+                       kNumCounters * 8 +
+                       (for_backward ? n_tile_pairs * (4 + 4 + 48 + 8 + 16 + 4) + (size_t)N * 24 + capacity * 24
+                                     : n_tile_pairs * (4 + 48) + capacity * 16) +
                        (rays ? R * 12 + (ntile + 1) * 8 : 0));
   a->blocks = keep.list;
   keep.keep = true;
@@ -540,6 +577,11 @@ mvp_status mvp_create(int device, mvp_ctx **out) {
   MVP_CHECK(resolve_scratch(device));
   mvp_ctx *c = new (std::nothrow) mvp_ctx(device);
   if (!c) { set_error("host allocation failed"); return MVP_ERR_OOM; }
+  const hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete c;
+    return status_of(e);
+  }
   *out = c;
   return MVP_OK;
 }
@@ -550,6 +592,10 @@ mvp_status mvp_destroy(mvp_ctx *ctx) {
   serve_shutdown(ctx);
   (void)mvp_timing_stop(ctx);
   (void)hipSetDevice(ctx->device);
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
   delete ctx;
   return MVP_OK;
 }
@@ -666,6 +712,7 @@ static mvp_status render_bwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *
                              const float *rgba, const mvp_ray_aux *aux, const float *grad_rgba, float *grad_payload,
                              float *grad_pos, float *grad_rot, float *grad_scale, float *grad_bg, hipStream_t s) {
   MVP_CHECK(check_render(ctx, a, prims));
+  if (!a->for_backward) { set_error("the structure was built for the forward only"); return MVP_ERR_INVALID; }
   if ((!aux || !grad_rgba) && a->n_slots > 0) { set_error("aux and grad_rgba are required"); return MVP_ERR_INVALID; }
   MVP_HIP(hipSetDevice(ctx->device));
   Blocks temp{ctx, s};
@@ -699,6 +746,7 @@ mvp_status mvp_render_bwd_noalloc(mvp_ctx *ctx, const mvp_accel *a, const mvp_pr
                                   const mvp_ray_aux *aux, const float *grad_rgba, float *grad_payload,
                                   float *grad_pos, float *grad_rot, float *grad_scale, void *stream) {
   MVP_CHECK(check_render(ctx, a, prims));
+  if (!a->for_backward) { set_error("the structure was built for the forward only"); return MVP_ERR_INVALID; }
   if ((!aux || !grad_rgba) && a->n_slots > 0) { set_error("aux and grad_rgba are required"); return MVP_ERR_INVALID; }
   if (a->n_rays() > (size_t)MVP_NOALLOC_MAX_RAYS) {
     set_error("%zu rays exceed the %d of the allocation-free backward (use mvp_render_bwd)", a->n_rays(),

@@ -78,6 +78,7 @@ struct KernelTimer {
 
 struct mvp_ctx {
   int device = 0;
+  hipStream_t side = nullptr;   // second stream for build work that can overlap the pairs kernel
   mvp::Arena arena;
   mvp::PinnedPool pinned;
   mvp::KernelTimer timer;
@@ -110,6 +111,7 @@ struct mvp_accel {
   uint32_t *ent_tile = nullptr;
   uint2 *ent_rec = nullptr;            // per-entry pair lists
   uint64_t pair_capacity = 0;
+  bool for_backward = true;            // false: no per-entry or transposed lists (forward only)
   hipEvent_t built = nullptr;          // recorded when the build's kernels have been enqueued
   int64_t n_slots = 0;                 // rays: V*H*W (full frames) or the subset size
   int64_t *ray_pix = nullptr;          // subset only: pixel id of each ray slot
@@ -148,10 +150,12 @@ struct Admit {
   mvp_status (*fn)(void *user, size_t bytes);
   void *user;
 };
-// rays == nullptr: every pixel of every view; else n_rays device pixel ids
+// rays == nullptr: every pixel of every view; else n_rays device pixel ids.
+// for_backward == false builds only what the forward reads (no per-entry pair
+// lists, no transposed lists): the serving loop's structures.
 mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams, int32_t n_views,
                        const mvp_march_params *params, const int64_t *rays, int64_t n_rays,
-                       mvp_accel **out, hipStream_t s, const Admit *admit);
+                       mvp_accel **out, hipStream_t s, const Admit *admit, bool for_backward = true);
 mvp_status destroy_accel(mvp_ctx *ctx, mvp_accel *a, hipStream_t s);
 // stop the serving scheduler of a context (waits for its work)
 void serve_shutdown(mvp_ctx *ctx);

@@ -668,7 +668,20 @@ __global__ __launch_bounds__(256) void k_payload_bound(const void *__restrict__ 
     c = fmaxf(c, __shfl_xor(c, d, kWave));
     sg = fmaxf(sg, __shfl_xor(sg, d, kWave));
   }
+  // one pair of atomics per workgroup: atomics on one address are serialised
+  // at the L2, so their number, not the payload read, sets this kernel's time
+  __shared__ float s_c[256 / kWave], s_s[256 / kWave];
+  const int wave = threadIdx.x / kWave;
   if ((threadIdx.x & (kWave - 1)) == 0) {
+    s_c[wave] = c;
+    s_s[wave] = sg;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 256 / kWave; ++w) {
+      c = fmaxf(c, s_c[w]);
+      sg = fmaxf(sg, s_s[w]);
+    }
     atomicMax(&pmax[0], __float_as_uint(c));
     atomicMax(&pmax[1], __float_as_uint(sg));
   }
@@ -1318,7 +1331,7 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
   if (e != hipSuccess) return e;
   const size_t n_vox = (size_t)p.n_prim * p.M * p.M * p.M;
   if (n_vox) {
-    const unsigned pg = (unsigned)std::min<size_t>((n_vox + 255) / 256, 2048);
+    const unsigned pg = (unsigned)std::min<size_t>((n_vox + 255) / 256, 1024);
     if (bf16)
       hipLaunchKernelGGL((k_payload_bound<true>), dim3(pg), dim3(256), 0, s, p.payload, n_vox, pmax);
     else

@@ -232,7 +232,8 @@ void Server::work(Slot &slot) {
     lk.unlock();
     Admit admit{&Server::admit_cb, &slot};
     mvp_accel *a = nullptr;
-    mvp_status st = build_accel(ctx_, &prims, &req.cam, 1, &req.params, nullptr, 0, &a, slot.stream, &admit);
+    mvp_status st = build_accel(ctx_, &prims, &req.cam, 1, &req.params, nullptr, 0, &a, slot.stream, &admit,
+                                 /*for_backward=*/false);
     if (st == MVP_OK) {
       slot.accel = a;
       hipError_t e = launch_zero_u64((uint64_t *)a->counters, kCntFwdPab + 1, slot.stream);

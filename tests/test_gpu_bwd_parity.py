@@ -152,8 +152,8 @@ def test_autograd_function_matches_direct_backward(mvp_ctx):
 
 @pytest.mark.parametrize("m", [16, 20], ids=["M16-lds", "M20-global"])
 def test_large_grid_gradients(mvp_ctx, m):
-    """M=16 accumulates a primitive's gradient in a 128 KiB FP64 copy in LDS;
-    M=20 does not fit and accumulates straight into device memory."""
+    """M=16 accumulates a primitive's gradient in a 128 KiB 64-bit fixed-point
+    copy in LDS; M=20 does not fit and accumulates straight into device memory."""
     prims = scenes.random_box_scene(91, n=5, m=m, s_lo=0.3, s_hi=0.6)
     cam = scenes.look_at_camera(np.random.default_rng(92), 40, 40)
     params = scenes.MarchParams(1 / 256, 1e-4)
@@ -170,8 +170,8 @@ def test_large_grid_gradients(mvp_ctx, m):
 def test_work_item_beyond_the_ordering_buffer(mvp_ctx):
     """A work item with more pairs than the LDS left for ordering them replays
     its pairs in list order.  One 16^3 primitive filling a 128x64 view gives one
-    work item of 32 fully covered tiles, 8192 pairs; with the FP64 gradient
-    copy (131 KB) in a 512-thread workgroup the ordering buffer holds 7936."""
+    work item of 32 fully covered tiles, 8192 pairs; with the 64-bit gradient
+    copy (131 KB) in a 512-thread workgroup the ordering buffer holds fewer."""
     rng = np.random.default_rng(95)
     prims = scenes.Prims(np.zeros((1, 3), np.float32), np.eye(3, dtype=np.float32)[None].copy(),
                          np.full((1, 3), 1.6, np.float32), scenes.random_payload(rng, 1, 16, 0.8))
