@@ -79,6 +79,8 @@ class Result:
     failed: int
     submit_lag_ms: List[float]  # submission - arrival (the client's own delay)
     overlapped: int             # requests whose [start, done] window overlaps another's
+    service_ms: List[float]     # done - start of the build (time on a slot)
+    pixels: List[int]           # the request's image size
 
 
 def _run(srv: Server, sids, reqs, params, arrivals: Optional[np.ndarray]) -> Result:
@@ -89,7 +91,7 @@ def _run(srv: Server, sids, reqs, params, arrivals: Optional[np.ndarray]) -> Res
     is held back for want of one."""
     n = len(reqs)
     pending = {}
-    lat, lag, windows = [], [], []
+    lat, lag, windows, serv, pix = [], [], [], [], []
     failed = 0
     t0 = srv.clock()
     i = 0
@@ -100,22 +102,24 @@ def _run(srv: Server, sids, reqs, params, arrivals: Optional[np.ndarray]) -> Res
             buf = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device="cuda")
             t = srv.submit(sids[si], cam, params, buf)
             arr = t0 + (arrivals[i] if arrivals is not None else 0.0)
-            pending[t] = (buf, arr)
+            pending[t] = (buf, arr, cam.width * cam.height)
             i += 1
         for t in list(pending):
             s, _, _ = srv.poll(t)
             if s >= 2:
-                _, arr = pending.pop(t)
+                _, arr, npx = pending.pop(t)
                 ts, tst, td = srv.times(t)
                 if s == 2:
                     lat.append((td - (arr if arrivals is not None else ts)) * 1e3)
                     lag.append((ts - arr) * 1e3)
                     windows.append((tst, td))
+                    serv.append((td - tst) * 1e3)
+                    pix.append(npx)
                 else:
                     failed += 1
                 srv.release(t)
         time.sleep(0.0002)
-    return Result(lat, srv.clock() - t0, n, failed, lag, count_overlapped(windows))
+    return Result(lat, srv.clock() - t0, n, failed, lag, count_overlapped(windows), serv, pix)
 
 
 def count_overlapped(windows) -> int:
@@ -165,6 +169,9 @@ def poisson_benchmark(ctx: Context, n_requests: int = 1000, seed: int = 5, n_sce
         failed += opened.failed
         lat = np.array(opened.latency_ms)
         lag = np.array(opened.submit_lag_ms)
+        serv = np.array(opened.service_ms)
+        big = np.array(opened.pixels) == max(opened.pixels) if opened.pixels else np.zeros(0, bool)
+        pct = lambda a, q: round(float(np.percentile(a, q)), 3) if a.size else None
         per_load.append({
             "load": load, "offered_fps": round(rate, 1),
             "achieved_fps": round((opened.n - opened.failed) / opened.wall_s, 1),
@@ -172,6 +179,11 @@ def poisson_benchmark(ctx: Context, n_requests: int = 1000, seed: int = 5, n_sce
             "p99_ms": round(float(np.percentile(lat, 99)), 3) if lat.size else None,
             "submit_lag_p99_ms": round(float(np.percentile(lag, 99)), 3) if lag.size else None,
             "overlapped": opened.overlapped,
+            # where the tail comes from: time on a slot (build + forward) against
+            # waiting, and the largest images against the rest
+            "service_p50_ms": pct(serv, 50), "service_p99_ms": pct(serv, 99),
+            "largest_p50_ms": pct(lat[big], 50), "largest_p99_ms": pct(lat[big], 99),
+            "others_p99_ms": pct(lat[~big], 99), "largest_share": round(float(big.mean()), 3) if big.size else None,
         })
     for s in sids:
         srv.release_scene(s)
