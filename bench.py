@@ -125,14 +125,22 @@ def cpu_baseline(size, views, n_rows):
 # memory traffic of the march kernels, from the kernels' own load counts
 # ----------------------------------------------------------------------------
 
-def fwd_bytes(lc, dtype, rays, aux=True):
+def fwd_bytes(lc, dtype, rays, aux=True, info=None):
     """Bytes k_march_fwd loads and stores per launch: voxel-corner sets (8
     corners), pair records (16 B) and culling-entry frames read from device
     memory (52 B: the tile's frames staged once per tile, or per pair for long
     lists) as counted by the kernel, plus per ray its segment and count (16 B)
-    and its outputs (rgba 16 B, aux 8 B)."""
-    return (lc["fwd_cells"] * 8 * VOX[dtype] + lc["fwd_pair_intervals"] * 16 + lc["fwd_pair_rays"] * 52
-            + rays * (16 + 16 + (8 if aux else 0)))
+    and its outputs (rgba 16 B, aux 8 B).  If `info` (the structure's sizes)
+    says the launch also built the pairs (pairs_in_forward), also:
+    per pair its record and entry-list record written (16 + 8 B), per
+    culling-list entry its id and primitive frame read (4 + 48 B) and its
+    frame, base, tile and four wave counts written (48 + 8 + 4 + 16 B), per
+    ray its segment and count written (16 B)."""
+    b = (lc["fwd_cells"] * 8 * VOX[dtype] + lc["fwd_pair_intervals"] * 16 + lc["fwd_pair_rays"] * 52
+         + rays * (16 + 16 + (8 if aux else 0)))
+    if info and info.get("pairs_in_forward"):
+        b += info["n_ray_pairs"] * 24 + info["n_tile_pairs"] * 128 + rays * 16
+    return b
 
 
 def bwd_bytes(lc, dtype, pose=True):
@@ -244,7 +252,7 @@ def kernel_report(m, dtype, rays, backward):
     lc = m["lc"]
     ps = lc["prim_samples"]
     out = {}
-    fb = fwd_bytes(lc, dtype, rays, aux=backward)
+    fb = fwd_bytes(lc, dtype, rays, aux=backward, info=m["info"])
     out[KERN_FWD] = {"ms": round(m["fwd_ms"], 3), "bytes": int(fb),
                      "gbs": round(fb / (m["fwd_ms"] / 1e3) / 1e9, 1),
                      "frac": round(fb / (m["fwd_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -124,6 +124,9 @@ typedef struct {
   int64_t n_tile_pairs;    /* (tile, primitive) entries of the culling lists           */
   int64_t n_ray_pairs;     /* (ray, primitive) pairs with at least one sample           */
   int64_t device_bytes;    /* device memory held by the structure                       */
+  int32_t pairs_in_forward; /* 1: the first forward builds the per-ray lists, tile by tile;
+                             * 0: the build's pairs kernel did                            */
+  int32_t reserved;
 } mvp_accel_info;
 
 /* ---- context ------------------------------------------------------------ */
@@ -146,8 +149,13 @@ const char *mvp_version(void);
  * the fixed-step sample interval inside each (the ray-specific lists and
  * domain of integration of Sec. 3.2.1).  cams is a HOST array of n_views.
  * Reads prims->pos/rot/scale; the payload is not read.  BLOCKS until the list
- * sizes are known (one stream synchronisation).  *out must be released with
- * mvp_accel_destroy. */
+ * sizes are known (one stream synchronisation).  The per-ray lists are built
+ * on the device by the first mvp_render_fwd* on the structure (each workgroup
+ * builds its screen tile's lists and then marches them), or by the first
+ * backward if it comes first; the lists the backward reads per primitive are
+ * built on the context's second stream after that first forward.  Calls on one
+ * structure must be ordered on the caller's streams.  *out must be released
+ * with mvp_accel_destroy. */
 mvp_status mvp_build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams,
                            int32_t n_views, const mvp_march_params *params,
                            mvp_accel **out, void *stream);
@@ -166,8 +174,10 @@ mvp_status mvp_build_accel_rays(mvp_ctx *ctx, const mvp_prims *prims, const mvp_
 /* Release an acceleration structure.  Its memory is recycled only after the
  * work already enqueued on `stream` has finished. */
 mvp_status mvp_accel_destroy(mvp_ctx *ctx, mvp_accel *accel, void *stream);
-/* Sizes of a structure.  The first call BLOCKS until the structure's build
- * has finished on the device (the pair count is counted there). */
+/* Sizes of a structure.  n_ray_pairs is counted on the device by the pass
+ * that builds the per-ray lists (the first forward or backward): it is -1
+ * until that pass has been enqueued, and the first call after it BLOCKS until
+ * it has finished. */
 mvp_status mvp_accel_get_info(const mvp_accel *accel, mvp_accel_info *info);
 
 /* Forward march (Sec. 3.2.2).  prims must be the primitives the structure was

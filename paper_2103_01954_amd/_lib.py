@@ -46,7 +46,7 @@ class mvp_ray_aux(C.Structure):
 class mvp_accel_info(C.Structure):
     _fields_ = [("n_views", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
                 ("n_prim", C.c_int32), ("n_tile_pairs", C.c_int64), ("n_ray_pairs", C.c_int64),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("pairs_in_forward", C.c_int32), ("reserved", C.c_int32)]
 
 
 class mvp_request(C.Structure):

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -85,6 +86,8 @@ Arena::~Arena() {
     for (void *b : p.blocks) free_.emplace(size_[b], b);
   }
   pending_.clear();
+  for (hipEvent_t e : events_) (void)hipEventDestroy(e);
+  events_.clear();
   trim_locked();
   for (auto &kv : size_) (void)hipFree(kv.first);   // blocks still owned by live objects
 }
@@ -92,7 +95,7 @@ Arena::~Arena() {
 void Arena::reap_locked() {
   for (size_t i = 0; i < pending_.size();) {
     if (hipEventQuery(pending_[i].ev) == hipSuccess) {
-      (void)hipEventDestroy(pending_[i].ev);
+      events_.push_back(pending_[i].ev);
       for (void *b : pending_[i].blocks) free_.emplace(size_[b], b);
       pending_[i] = pending_.back();
       pending_.pop_back();
@@ -125,13 +128,16 @@ size_t Arena::held_bytes() {
 mvp_status Arena::alloc(size_t bytes, void **out) {
   const size_t sz = round_size(bytes);
   std::lock_guard<std::mutex> g(mu_);
-  reap_locked();
-  auto it = free_.lower_bound(sz);
-  if (it != free_.end() && it->first <= 2 * sz) {
+  auto fit = [&]() {
+    auto it = free_.lower_bound(sz);
+    if (it == free_.end() || it->first > 2 * sz) return false;
     *out = it->second;
     free_.erase(it);
-    return MVP_OK;
-  }
+    return true;
+  };
+  if (fit()) return MVP_OK;
+  reap_locked();   // blocks whose streams have passed their release points
+  if (fit()) return MVP_OK;
   void *p = nullptr;
   hipError_t e = hipMalloc(&p, sz);
   if (e == hipErrorOutOfMemory) {
@@ -156,15 +162,39 @@ void Arena::release_now(void *p) {
   free_.emplace(size_[p], p);
 }
 
+mvp_status Arena::get_event(hipEvent_t *ev) {
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    if (!events_.empty()) {
+      *ev = events_.back();
+      events_.pop_back();
+      return MVP_OK;
+    }
+  }
+  const hipError_t e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    set_error("event creation failed: %s", hipGetErrorString(e));
+    return status_of(e);
+  }
+  return MVP_OK;
+}
+
+void Arena::put_event(hipEvent_t ev) {
+  if (!ev) return;
+  std::lock_guard<std::mutex> g(mu_);
+  events_.push_back(ev);
+}
+
 mvp_status Arena::release_after(const std::vector<void *> &blocks, hipStream_t s) {
   if (blocks.empty()) return MVP_OK;
-  hipEvent_t ev;
-  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  hipEvent_t ev = nullptr;
+  hipError_t e = get_event(&ev) == MVP_OK ? hipSuccess : hipErrorOutOfMemory;
   if (e == hipSuccess) e = hipEventRecord(ev, s);
   std::lock_guard<std::mutex> g(mu_);
   if (e != hipSuccess) {
     // cannot track completion: wait for the stream instead
     (void)hipStreamSynchronize(s);
+    if (ev) events_.push_back(ev);
     for (void *b : blocks) free_.emplace(size_[b], b);
     set_error("event record failed: %s", hipGetErrorString(e));
     return MVP_ERR_DEVICE;
@@ -266,6 +296,37 @@ static mvp_status read_u64(const uint64_t *dev, uint64_t *host, hipStream_t s) {
   return MVP_OK;
 }
 
+// The transposed lists (primitive -> its culling-list entries) and the
+// backward work items, on the context's side stream after the build's kernels
+// (event `built`); they need only the sorted culling lists.  Launched once, by
+// the first forward after its own launch or by the first backward; `lists` is
+// recorded after them and the held temporaries are recycled after them.
+static mvp_status launch_lists(const mvp_accel *ac) {
+  if (!ac->lists_pending.exchange(false)) return MVP_OK;
+  mvp_accel *a = const_cast<mvp_accel *>(ac);
+  mvp_ctx *ctx = a->ctx;
+  hipStream_t s2 = ctx->side;
+  const AccelView av = a->view(2);
+  const size_t N = (size_t)a->N;
+  const uint64_t ne = (uint64_t)a->n_tile_pairs;
+  hipError_t e = hipStreamWaitEvent(s2, a->built, 0);
+  if (e == hipSuccess) e = launch_zero_u32(a->prim_cnt, N, s2);
+  if (e == hipSuccess) e = launch_prim_entry_count(a->tile_list, ne, a->prim_cnt, s2);
+  if (e == hipSuccess) e = launch_scan_u32_u64(a->prim_cnt, a->prim_entry_off, N, a->scan_scratch, s2);
+  if (e == hipSuccess) e = launch_prim_entry_place(av, a->rect, ne, a->prim_entry_off, a->prim_entries, s2);
+  if (e == hipSuccess) e = launch_item_count(a->prim_entry_off, a->N, a->item_entries, a->prim_cnt, s2);
+  if (e == hipSuccess) e = launch_scan_u32_u64(a->prim_cnt, a->item_off, N, a->scan_scratch, s2);
+  if (e == hipSuccess) e = hipEventRecord(a->lists, s2);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(s2);
+    a->lists_pending.store(true);   // a later call tries again
+    MVP_HIP(e);
+  }
+  MVP_CHECK(ctx->arena.release_after(a->lists_temps, s2));
+  a->lists_temps.clear();
+  return MVP_OK;
+}
+
 mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *cams, int32_t n_views,
                        const mvp_march_params *params, const int64_t *rays, int64_t n_rays,
                        mvp_accel **out, hipStream_t s, const Admit *admit, bool for_backward) {
@@ -314,13 +375,13 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
     bool keep = false;
     ~Guard() {
       if (keep) return;
-      if (a->built) (void)hipEventDestroy(a->built);
+      for (hipEvent_t e : {a->built, a->lists, a->pairs_done}) a->ctx->arena.put_event(e);
       delete a;
     }
   } guard{a};
 
   MVP_HIP(hipSetDevice(ctx->device));
-  Blocks keep{ctx, s}, temp{ctx, s};
+  Blocks keep{ctx, s}, temp{ctx, s}, ltmp{ctx, s};   // ltmp: temporaries the transposed lists read
   int4 *rect = nullptr;
   uint32_t *tile_cnt = nullptr, *cap = nullptr, *rcnt = nullptr, *depth = nullptr;
   uint8_t *scratch = nullptr;
@@ -338,11 +399,11 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   MVP_CHECK(keep.get(&a->ray_seg, R ? R : 1));
   MVP_CHECK(keep.get(&a->ray_nj, R ? R : 1));
   MVP_CHECK(keep.get(&a->counters, kNumCounters));
-  MVP_CHECK(temp.get(&rect, (size_t)n_views * N));
+  MVP_CHECK(ltmp.get(&rect, (size_t)n_views * N));
   MVP_CHECK(temp.get(&depth, (size_t)n_views * N));
   MVP_CHECK(temp.get(&tile_cnt, ntile));
   MVP_CHECK(temp.get(&cap, ntile));
-  MVP_CHECK(temp.get(&scratch, sb));
+  MVP_CHECK(ltmp.get(&scratch, sb));
   // cameras up and list sizes down through a pinned block (returned once the
   // build has synchronised, or on any early return)
   struct PinHold {
@@ -429,7 +490,7 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
     MVP_CHECK(keep.get(&a->ent_n, 4 * ntp));
     MVP_CHECK(keep.get(&a->ent_tile, ntp));
     MVP_CHECK(keep.get(&a->ent_rec, npc));
-    MVP_CHECK(temp.get(&prim_cnt, (size_t)N + 1));
+    MVP_CHECK(ltmp.get(&prim_cnt, (size_t)N + 1));
   }
   av = a->view(2);
   MVP_HIP(launch_zero_u32(tile_cnt, ntile, s));
@@ -437,50 +498,26 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   MVP_HIP(launch_segment_sort(a->tile_off, a->tile_list, (int64_t)ntile, depth, N, tx * ty, s));
   a->item_entries = backward_item_entries(prims->M);
   a->n_items_max = for_backward ? (int64_t)(n_tile_pairs / a->item_entries) + N : 0;
-  if (!for_backward) {
-    MVP_HIP(launch_pairs(av, a->ef, a->pr, a->ray_seg, a->ray_nj, nullptr, nullptr, nullptr, nullptr,
-                         a->counters + kCntPairs, s));
-  } else {
-    // The transposed lists (primitive -> its entries) and the backward work
-    // items need only the sorted culling lists: they run on the context's side
-    // stream while the pairs kernel (every ray's pairs, the entry frames and the
-    // per-entry pair lists) runs on the build's stream, which then waits for
-    // them, so everything enqueued after the build (and the recycling of the
-    // temporaries) follows both.
-    struct Events {
-      hipEvent_t fork = nullptr, join = nullptr;
-      ~Events() {
-        if (fork) (void)hipEventDestroy(fork);
-        if (join) (void)hipEventDestroy(join);
-      }
-    } ev;
-    MVP_HIP(hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming));
-    MVP_HIP(hipEventCreateWithFlags(&ev.join, hipEventDisableTiming));
-    MVP_HIP(hipEventRecord(ev.fork, s));
-    MVP_HIP(hipStreamWaitEvent(ctx->side, ev.fork, 0));
-    hipError_t te = hipSuccess;
-    {
-      hipStream_t s2 = ctx->side;
-      auto run = [&](hipError_t e) { if (te == hipSuccess) te = e; };
-      run(launch_zero_u32(prim_cnt, (size_t)N, s2));
-      if (te == hipSuccess) run(launch_prim_entry_count(a->tile_list, n_tile_pairs, prim_cnt, s2));
-      if (te == hipSuccess) run(launch_scan_u32_u64(prim_cnt, a->prim_entry_off, (size_t)N, scratch, s2));
-      if (te == hipSuccess)
-        run(launch_prim_entry_place(av, rect, n_tile_pairs, a->prim_entry_off, a->prim_entries, s2));
-      if (te == hipSuccess) run(launch_item_count(a->prim_entry_off, N, a->item_entries, prim_cnt, s2));
-      if (te == hipSuccess) run(launch_scan_u32_u64(prim_cnt, a->item_off, (size_t)N, scratch, s2));
-    }
-    const hipError_t pe = launch_pairs(av, a->ef, a->pr, a->ray_seg, a->ray_nj, a->ent_base, a->ent_n, a->ent_tile,
-                                       a->ent_rec, a->counters + kCntPairs, s);
-    hipError_t je = hipEventRecord(ev.join, ctx->side);
-    if (je == hipSuccess) je = hipStreamWaitEvent(s, ev.join, 0);
-    if (je != hipSuccess) (void)hipStreamSynchronize(ctx->side);   // no temporary may be recycled under it
-    MVP_HIP(je);
-    MVP_HIP(te);
-    MVP_HIP(pe);
+  // Every ray's pairs, the entry frames and the per-entry pair lists: either
+  // by the pairs kernel now, or by the first forward, each workgroup building
+  // its tile's pairs just before marching them.  Fusing pays where the march
+  // has latency to hide the pairs pass in (payloads of at most 8^3, which stay
+  // in the caches) and the grid has enough tiles (32 per CU) for the pairs
+  // phases of some workgroups to overlap the marching of others; elsewhere the
+  // pairs kernel, at its own higher occupancy, is faster.
+  a->po = PairsOut{a->ef, a->pr, a->ray_seg, a->ray_nj, a->ent_base, a->ent_n, a->ent_tile, a->ent_rec,
+                   a->counters + kCntPairs};
+  // MVP_PAIRS_IN_FORWARD=1 or 0 overrides the choice (tests and tuning)
+  const char *force = getenv("MVP_PAIRS_IN_FORWARD");
+  const bool fuse = force && (force[0] == '0' || force[0] == '1') ? force[0] == '1' : prims->M <= 8 && ntile >= 8192;
+  MVP_CHECK(ctx->arena.get_event(&a->pairs_done));
+  if (for_backward) MVP_CHECK(ctx->arena.get_event(&a->lists));
+  MVP_CHECK(ctx->arena.get_event(&a->built));
+  MVP_HIP(hipEventRecord(a->built, s));   // the culling lists are complete
+  if (!fuse) {
+    MVP_HIP(launch_pairs(av, a->po, s));
+    MVP_HIP(hipEventRecord(a->pairs_done, s));
   }
-  MVP_HIP(hipEventCreateWithFlags(&a->built, hipEventDisableTiming));
-  MVP_HIP(hipEventRecord(a->built, s));
 
   a->n_tile_pairs = (int64_t)n_tile_pairs;
   a->n_ray_pairs = -1;   // read from the device on demand (mvp_accel_get_info)
@@ -492,20 +529,40 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
                        (rays ? R * 12 + (ntile + 1) * 8 : 0));
   a->blocks = keep.list;
   keep.keep = true;
-  // temporaries are recycled once the pairs kernel has run
+  // temporaries are recycled once the build's kernels have run, except those
+  // of the transposed lists, which the structure holds until they are launched
+  // (now, beside the pairs kernel; or after the first forward when that builds
+  // the pairs, so that their launches are off the path to the forward)
   MVP_CHECK(ctx->arena.release_after(temp.list, s));
   temp.keep = true;
+  if (for_backward) {
+    a->rect = rect;
+    a->prim_cnt = prim_cnt;
+    a->scan_scratch = scratch;
+    a->lists_temps = ltmp.list;
+    ltmp.keep = true;
+    a->lists_pending.store(true);
+  }
+  a->pairs_pending.store(fuse);
+  a->pairs_in_forward = fuse;
   guard.keep = true;
   ctx->live_accels.fetch_add(1);
   *out = a;
+  // beside the pairs kernel; on failure the first backward tries again
+  if (!fuse) (void)launch_lists(a);
   return MVP_OK;
 }
 
 mvp_status destroy_accel(mvp_ctx *ctx, mvp_accel *a, hipStream_t s) {
   if (!ctx || !a || a->ctx != ctx) { set_error("bad accel handle"); return MVP_ERR_INVALID; }
+  if (a->lists_pending.exchange(false)) {
+    (void)ctx->arena.release_after(a->lists_temps, s);   // never launched: last used by the build
+  } else if (a->lists) {
+    (void)hipStreamWaitEvent(s, a->lists, 0);   // the transposed lists are written on the side stream
+  }
   mvp_status st = ctx->arena.release_after(a->blocks, s);
   ctx->live_accels.fetch_sub(1);
-  if (a->built) (void)hipEventDestroy(a->built);
+  for (hipEvent_t e : {a->built, a->lists, a->pairs_done}) ctx->arena.put_event(e);
   delete a;
   return st;
 }
@@ -620,15 +677,17 @@ mvp_status mvp_accel_destroy(mvp_ctx *ctx, mvp_accel *accel, void *stream) {
 
 mvp_status mvp_accel_get_info(const mvp_accel *a, mvp_accel_info *info) {
   if (!a || !info) { set_error("NULL argument"); return MVP_ERR_INVALID; }
-  if (a->n_ray_pairs < 0) {   // the pairs kernel counts them on the device
+  if (a->n_ray_pairs < 0 && !a->pairs_pending.load()) {   // counted on the device by the pass that built them
     MVP_HIP(hipSetDevice(a->ctx->device));
-    MVP_HIP(hipEventSynchronize(a->built));
+    MVP_HIP(hipEventSynchronize(a->pairs_done));
     uint64_t n = 0;
     MVP_HIP(hipMemcpy(&n, a->counters + kCntPairs, sizeof n, hipMemcpyDeviceToHost));
     const_cast<mvp_accel *>(a)->n_ray_pairs = (int64_t)n;
   }
   info->n_views = a->V; info->width = a->W; info->height = a->H; info->n_prim = a->N;
   info->n_tile_pairs = a->n_tile_pairs; info->n_ray_pairs = a->n_ray_pairs; info->device_bytes = a->bytes;
+  info->pairs_in_forward = a->pairs_in_forward ? 1 : 0;
+  info->reserved = 0;
   return MVP_OK;
 }
 
@@ -703,8 +762,27 @@ static mvp_status render_fwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *
   MVP_HIP(launch_zero_u64((uint64_t *)a->counters, kCntFwdPab + 1, s));
   const auto ev = timer_slot(ctx, MVP_KERNEL_FWD_MARCH);
   if (ev.first) MVP_HIP(hipEventRecord(ev.first, s));
-  MVP_HIP(launch_march_fwd(a->view(prims->M), *prims, bg, rgba, aux, a->counters, s));
+  // the first forward builds the pairs, tile by tile, before marching them
+  const bool build = a->pairs_pending.exchange(false);
+  hipError_t e = launch_march_fwd(a->view(prims->M), *prims, bg, rgba, aux, a->counters, s, build ? &a->po : nullptr);
+  if (e == hipSuccess && build) e = hipEventRecord(a->pairs_done, s);
+  if (e != hipSuccess && build) a->pairs_pending.store(true);
+  MVP_HIP(e);
   if (ev.second) MVP_HIP(hipEventRecord(ev.second, s));
+  return launch_lists(a);
+}
+
+// What the backward reads of the structure: the pairs (built here if no
+// forward has built them) and the transposed lists (made on the side stream).
+static mvp_status bwd_ready(const mvp_accel *a, hipStream_t s) {
+  if (a->pairs_pending.exchange(false)) {
+    hipError_t e = launch_pairs(a->view(2), a->po, s);
+    if (e == hipSuccess) e = hipEventRecord(a->pairs_done, s);
+    if (e != hipSuccess) a->pairs_pending.store(true);
+    MVP_HIP(e);
+  }
+  MVP_CHECK(launch_lists(a));
+  if (a->lists) MVP_HIP(hipStreamWaitEvent(s, a->lists, 0));
   return MVP_OK;
 }
 
@@ -715,6 +793,7 @@ static mvp_status render_bwd(mvp_ctx *ctx, const mvp_accel *a, const mvp_prims *
   if (!a->for_backward) { set_error("the structure was built for the forward only"); return MVP_ERR_INVALID; }
   if ((!aux || !grad_rgba) && a->n_slots > 0) { set_error("aux and grad_rgba are required"); return MVP_ERR_INVALID; }
   MVP_HIP(hipSetDevice(ctx->device));
+  MVP_CHECK(bwd_ready(a, s));
   Blocks temp{ctx, s};
   uint8_t *scratch = nullptr;
   MVP_CHECK(temp.get(&scratch, bwd_scratch_bytes(a->n_rays())));
@@ -756,6 +835,7 @@ mvp_status mvp_render_bwd_noalloc(mvp_ctx *ctx, const mvp_accel *a, const mvp_pr
   void *ptr = (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_scratch[ctx->device] : nullptr;
   if (!ptr) { set_error("the backward scratch array of device %d was not resolved", ctx->device); return MVP_ERR_DEVICE; }
   MVP_HIP(hipSetDevice(ctx->device));
+  MVP_CHECK(bwd_ready(a, (hipStream_t)stream));
   const auto ev = timer_slot(ctx, MVP_KERNEL_BWD_MARCH);
   MVP_HIP(launch_march_bwd(a->view(prims->M), *prims, a->n_items_max, aux, grad_rgba, nullptr, nullptr, ptr,
                            grad_payload, grad_pos, grad_rot, grad_scale, nullptr, a->counters, (hipStream_t)stream,

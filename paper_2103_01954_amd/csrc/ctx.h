@@ -31,6 +31,11 @@ class Arena {
   void release_now(void *p);
   size_t held_bytes();
   void trim();
+  // Events without timing, recycled (creating one costs microseconds of host
+  // time on the build's path).  An event handed back may still be pending:
+  // recording it again later is fine.
+  mvp_status get_event(hipEvent_t *ev);
+  void put_event(hipEvent_t ev);
 
  private:
   struct Pending {
@@ -44,6 +49,7 @@ class Arena {
   std::multimap<size_t, void *> free_;
   std::unordered_map<void *, size_t> size_;
   std::vector<Pending> pending_;
+  std::vector<hipEvent_t> events_;
   size_t held_ = 0;
 };
 
@@ -112,7 +118,24 @@ struct mvp_accel {
   uint2 *ent_rec = nullptr;            // per-entry pair lists
   uint64_t pair_capacity = 0;
   bool for_backward = true;            // false: no per-entry or transposed lists (forward only)
-  hipEvent_t built = nullptr;          // recorded when the build's kernels have been enqueued
+  bool pairs_in_forward = false;       // the first forward builds the pairs
+  hipEvent_t built = nullptr;          // recorded on the build's stream after its kernels
+  hipEvent_t lists = nullptr;          // recorded on the side stream once the transposed lists are built
+  // The per-ray pairs are built by the first forward (each workgroup builds its
+  // tile's pairs, then marches them) or, if a backward comes first, by the
+  // pairs kernel; pairs_done is recorded after whichever did it.
+  mvp::PairsOut po{};
+  mutable std::atomic<bool> pairs_pending{false};
+  mutable hipEvent_t pairs_done = nullptr;
+  // The transposed lists are built on the context's side stream, launched
+  // after the first forward (so that their launches are off the path from
+  // the build to the forward) or by the first backward; until then the
+  // structure keeps the temporaries they read.
+  mutable std::atomic<bool> lists_pending{false};
+  std::vector<void *> lists_temps;
+  int4 *rect = nullptr;
+  uint32_t *prim_cnt = nullptr;
+  uint8_t *scan_scratch = nullptr;
   int64_t n_slots = 0;                 // rays: V*H*W (full frames) or the subset size
   int64_t *ray_pix = nullptr;          // subset only: pixel id of each ray slot
   uint64_t *tile_ray_off = nullptr;    // subset only

@@ -105,6 +105,21 @@ struct AccelView {
   const uint32_t *tile_rays;   // or nullptr
 };
 
+// Where a tile's pairs go (see AccelView for the layouts).  Not restrict: the
+// forward march reads them back through its AccelView after a barrier.  The
+// per-entry lists (ent_*) are null for a structure built for the forward only.
+struct PairsOut {
+  float4 *ef;
+  int4 *pr;
+  uint64_t *ray_seg;
+  int2 *ray_nj;
+  uint64_t *ent_base;
+  uint32_t *ent_n;
+  uint32_t *ent_tile;
+  uint2 *ent_rec;
+  unsigned long long *n_pairs;
+};
+
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2):
 // workgroup b runs on XCD b % 8.  Launching kXcd * ceil(n / kXcd) workgroups and
 // mapping b -> (b % kXcd) * per + b / kXcd gives every XCD a contiguous band of
@@ -276,17 +291,18 @@ hipError_t launch_tile_capacity(const uint32_t *tile_cnt, const uint32_t *tile_r
                                 hipStream_t s);
 // the (ray, primitive) pairs of every ray, the entry frames and the per-entry
 // pair lists (see AccelView); adds the number of pairs to *n_pairs
-hipError_t launch_pairs(const AccelView &av, float4 *ef, int4 *pr, uint64_t *ray_seg, int2 *ray_nj,
-                        uint64_t *ent_base, uint32_t *ent_n, uint32_t *ent_tile, uint2 *ent_rec,
-                        unsigned long long *n_pairs, hipStream_t s);
+hipError_t launch_pairs(const AccelView &av, const PairsOut &o, hipStream_t s);
 // debug hit sets: per ray the number of slab hits (with or without samples),
 // then their primitive ids in increasing order at ids[off[ray] ..]
 hipError_t launch_hit_count(const AccelView &av, uint32_t *ray_cnt, hipStream_t s);
 hipError_t launch_hit_ids(const AccelView &av, const uint64_t *off, int32_t *ids, hipStream_t s);
 
 // bg: optional background [rays,3] composited under the premultiplied colour
+// build_pairs != nullptr: each workgroup first computes its tile's pairs (as
+// launch_pairs does) and then marches them.
 hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, const float *bg, float *rgba,
-                            mvp_ray_aux *aux, unsigned long long *counters, hipStream_t s);
+                            mvp_ray_aux *aux, unsigned long long *counters, hipStream_t s,
+                            const PairsOut *build_pairs = nullptr);
 // backward; scratch holds bwd_scratch_bytes(n_slots) bytes (nothing in it needs
 // to start at zero); bg/rgba/g_bg for a composited forward
 hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_items_max,

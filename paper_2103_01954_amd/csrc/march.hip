@@ -45,6 +45,7 @@
 #include <climits>
 
 #include "internal.h"
+#include "pairs.h"
 
 namespace mvp {
 
@@ -453,10 +454,13 @@ __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay
 // this many entries.
 constexpr int kFrameLds = 256;
 
-template <bool BF16, bool FADE>
+// BUILD: the workgroup first builds its tile's pairs (the pairs pass of the
+// build, tile_pairs), then marches them; the records it reads back were
+// written by other threads of the workgroup before the barrier.
+template <bool BF16, bool FADE, bool BUILD>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_march_fwd(
     AccelView av, const void *__restrict__ pay, const float *__restrict__ bg, float4 *__restrict__ rgba,
-    mvp_ray_aux *__restrict__ aux, unsigned long long *__restrict__ counters) {
+    mvp_ray_aux *__restrict__ aux, unsigned long long *__restrict__ counters, PairsOut po) {
   __shared__ int s_list[kTileThreads];
   __shared__ int s_wave[kTileThreads / kWave];
   __shared__ float4 s_frm[4 * kFrameLds];
@@ -465,6 +469,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3)
   const int slot = xcd_tile(blockIdx.x, av.V * av.tiles_x * av.tiles_y);
   if (slot < 0) return;
   const int tile = blocked_tile(slot, av.tiles_x, av.tiles_y);
+  if (BUILD) {
+    tile_pairs(av, tile, po);
+    __syncthreads();
+  }
   if (FADE) fill_fade(s_fade, av.M, av.fade_alpha, av.fade_beta);   // visible after compact_tile's barrier
   const uint64_t lb = av.tile_off[tile], len = av.tile_off[tile + 1] - lb;
   const bool staged = len <= (uint64_t)kFrameLds;
@@ -526,19 +534,27 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3)
 }
 
 hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, const float *bg, float *rgba,
-                            mvp_ray_aux *aux, unsigned long long *counters, hipStream_t s) {
+                            mvp_ray_aux *aux, unsigned long long *counters, hipStream_t s,
+                            const PairsOut *build_pairs) {
   const int ntile = av.V * av.tiles_x * av.tiles_y;
   if (ntile == 0) return hipSuccess;
   const bool fade = av.fade_alpha > 0.f;
   const size_t shm = fade ? (size_t)av.M * sizeof(float) : 0;
-#define MVP_FWD(B, F)                                                                                  \
-  hipLaunchKernelGGL((k_march_fwd<B, F>), dim3(xcd_grid(ntile)), dim3(kTileThreads), shm, s, av, p.payload, bg, \
-                     (float4 *)rgba, aux, counters)
+  const PairsOut po = build_pairs ? *build_pairs : PairsOut{};
+#define MVP_FWD(B, F, P)                                                                                     \
+  hipLaunchKernelGGL((k_march_fwd<B, F, P>), dim3(xcd_grid(ntile)), dim3(kTileThreads), shm, s, av, p.payload, \
+                     bg, (float4 *)rgba, aux, counters, po)
+#define MVP_FWD_P(B, F)                  \
+  do {                                   \
+    if (build_pairs) MVP_FWD(B, F, true); \
+    else MVP_FWD(B, F, false);           \
+  } while (0)
   if (p.payload_dtype == MVP_BF16) {
-    if (fade) MVP_FWD(true, true); else MVP_FWD(true, false);
+    if (fade) MVP_FWD_P(true, true); else MVP_FWD_P(true, false);
   } else {
-    if (fade) MVP_FWD(false, true); else MVP_FWD(false, false);
+    if (fade) MVP_FWD_P(false, true); else MVP_FWD_P(false, false);
   }
+#undef MVP_FWD_P
 #undef MVP_FWD
   return hipGetLastError();
 }

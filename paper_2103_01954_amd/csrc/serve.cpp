@@ -238,7 +238,8 @@ void Server::work(Slot &slot) {
       slot.accel = a;
       hipError_t e = launch_zero_u64((uint64_t *)a->counters, kCntFwdPab + 1, slot.stream);
       if (e == hipSuccess)
-        e = launch_march_fwd(a->view(prims.M), prims, nullptr, req.rgba_out, nullptr, a->counters, slot.stream);
+        e = launch_march_fwd(a->view(prims.M), prims, nullptr, req.rgba_out, nullptr, a->counters, slot.stream,
+                             a->pairs_pending.exchange(false) ? &a->po : nullptr);
       if (e == hipSuccess) e = hipLaunchHostFunc(slot.stream, &Server::host_done, &slot);
       if (e != hipSuccess) {
         set_error("launch failed: %s", hipGetErrorString(e));
