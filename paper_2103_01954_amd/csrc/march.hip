@@ -642,18 +642,28 @@ __global__ __launch_bounds__(256) void k_bwd_rays(AccelView av, const void *__re
         T = Tn;
       }
     } else {
+      // the pairs open at S, in list order (the order the forward summed them
+      // in); their records are read four at a time, so that the scan does not
+      // wait for one record before asking for the next
       float sig = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
-      for (int i = 0; i < n; ++i) {
-        const int4 pq = av.pr[seg + i * stride];
-        if (pq.x > ax.j_end) break;          // sorted by first sample
-        if (pq.y < ax.j_end) continue;
-        float4 A, B;
-        fr.local(av, pq.z, Dir{d, 1}, A, B);
-        const float4 s = sample_pair<BF16, FADE>(av, pay, s_fade, A, B, tau);
-        sig += s.w;
-        c0 = fmaf(s.w, s.x, c0);
-        c1 = fmaf(s.w, s.y, c1);
-        c2 = fmaf(s.w, s.z, c2);
+      constexpr int kB = 4;
+      for (int i0 = 0; i0 < n; i0 += kB) {
+        int4 q[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k)
+          q[k] = i0 + k < n ? av.pr[seg + (i0 + k) * stride] : make_int4(INT_MAX, INT_MIN, 0, 0);
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+          if (q[k].x > ax.j_end || q[k].y < ax.j_end) continue;
+          float4 A, B;
+          fr.local(av, q[k].z, Dir{d, 1}, A, B);
+          const float4 s = sample_pair<BF16, FADE>(av, pay, s_fade, A, B, tau);
+          sig += s.w;
+          c0 = fmaf(s.w, s.x, c0);
+          c1 = fmaf(s.w, s.y, c1);
+          c2 = fmaf(s.w, s.z, c2);
+        }
+        if (q[kB - 1].x > ax.j_end) break;   // sorted by first sample: no later pair is open
       }
       tdot = -(g.x * (c0 / sig) + g.y * (c1 / sig) + g.z * (c2 / sig));
       wsig = (1.0f - ax.t_prev) / sig;
