@@ -410,7 +410,8 @@ hipError_t launch_item_count(const uint64_t *prim_entry_off, int n_prim, int per
 // tile's list runs from near to far and a ray meets its primitives nearly in
 // the order of their first samples; ties and the order itself are
 // independent of the order of the fill atomics.  Bitonic sort in LDS;
-// segments longer than kSortMax fall back to a heapsort by one thread.
+// segments longer than kSortMax are sorted by the same network in device
+// memory.
 constexpr int kSortMax = 4096;
 
 __device__ __forceinline__ uint64_t sort_key(uint32_t x, const uint32_t *depth, uint64_t vN) {
@@ -449,25 +450,39 @@ __global__ __launch_bounds__(256) void k_segment_sort(const uint64_t *__restrict
     for (int i = threadIdx.x; i < n; i += blockDim.x) list[b + i] = (uint32_t)s[i];
     return;
   }
-  if (threadIdx.x != 0) return;
+  // Longer segments: the same sort over the segment in device memory (in place,
+  // keys looked up as they are compared), in the form of the bitonic network
+  // whose comparators all put the smaller key first, so that the entries past
+  // n act as +infinity and never move.  Each stage's comparators are
+  // independent, so a thread issues several at once; a barrier separates the
+  // stages (the workgroup's writes are visible to it after the barrier).
   uint32_t *a = list + b;
-  auto key = [&](int64_t i) { return sort_key(a[i], depth, vN); };
-  auto sift = [&](int64_t root, int64_t end) {
-    while (2 * root + 1 < end) {
-      int64_t child = 2 * root + 1;
-      if (child + 1 < end && key(child) < key(child + 1)) ++child;
-      if (key(root) < key(child)) {
-        const uint32_t t = a[root]; a[root] = a[child]; a[child] = t;
-        root = child;
-      } else {
-        return;
-      }
+  int64_t np = 2;
+  while (np < n) np <<= 1;
+  const int64_t half = np >> 1;
+  auto cmpx = [&](int64_t i, int64_t q) {
+    if (q >= n) return;
+    const uint32_t x = a[i], y = a[q];
+    if (sort_key(x, depth, vN) > sort_key(y, depth, vN)) {
+      a[i] = y;
+      a[q] = x;
     }
   };
-  for (int64_t i = n / 2; i-- > 0;) sift(i, n);
-  for (int64_t end = n - 1; end > 0; --end) {
-    const uint32_t t = a[0]; a[0] = a[end]; a[end] = t;
-    sift(0, end);
+  for (int64_t k = 2; k <= np; k <<= 1) {
+    const int64_t hk = k >> 1;
+    for (int64_t c = threadIdx.x; c < half; c += blockDim.x) {   // flip: i against its mirror in the k-block
+      const int64_t i = (c / hk) * k + (c % hk);
+      cmpx(i, (i / k) * k + (k - 1 - (i % k)));
+    }
+    __syncthreads();
+    for (int64_t j = hk >> 1; j > 0; j >>= 1) {   // half-cleaners
+#pragma unroll 4
+      for (int64_t c = threadIdx.x; c < half; c += blockDim.x) {
+        const int64_t i = (c / j) * 2 * j + (c % j);
+        cmpx(i, i + j);
+      }
+      __syncthreads();
+    }
   }
 }
 
