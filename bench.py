@@ -48,7 +48,7 @@ VOX = {"f32": 16, "bf16": 8}   # bytes of one voxel (4 channels)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--views", type=int, default=4)
@@ -226,23 +226,32 @@ class Runner:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         start.record(self.stream)
+        marks = [start]                   # one event per step boundary, for the median step
         last = None
-        for _ in range(steps):
+        for i in range(steps):
             acc = self.step()
             if last is not None:
                 last.destroy()
             last = acc
+            if i + 1 < steps:
+                e = torch.cuda.Event(enable_timing=True)
+                e.record(self.stream)
+                marks.append(e)
         stop.record(self.stream)
+        marks.append(stop)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = start.elapsed_time(stop) / steps
+        per_step = [a.elapsed_time(b) for a, b in zip(marks[:-1], marks[1:])]
         lc = last.load_counts()
         info = last.info()
         last.destroy()
         fwd_ms = float(np.mean(self.ctx.timing_read("fwd")))
         bwd_ms = float(np.mean(self.ctx.timing_read("bwd"))) if self.backward else None
         self.ctx.timing_stop()
-        return {"ms": ms, "wall": wall, "lc": lc, "info": info, "fwd_ms": fwd_ms, "bwd_ms": bwd_ms}
+        return {"ms": ms, "ms_median": float(np.median(per_step)), "ms_min": float(np.min(per_step)),
+                "ms_max": float(np.max(per_step)), "wall": wall, "lc": lc, "info": info,
+                "fwd_ms": fwd_ms, "bwd_ms": bwd_ms}
 
 
 def kernel_report(m, dtype, rays, backward):
@@ -463,6 +472,7 @@ def main():
             m2 = r2.measure(steps, warm)
             lc2 = m2["lc"]
             extra[name] = {"workload": desc2, "ms_per_step": round(m2["ms"], 3),
+                           "ms_per_step_median": round(m2["ms_median"], 3),
                            "msamples_s": round(lc2["ray_samples"] / (m2["ms"] / 1e3) / 1e6, 1),
                            "mprim_samples_s": round(lc2["prim_samples"] / (m2["ms"] / 1e3) / 1e6, 1),
                            "ray_samples": lc2["ray_samples"], "prim_samples": lc2["prim_samples"],
@@ -493,6 +503,8 @@ def main():
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "Msamples/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "ms_per_step_median": round(m["ms_median"], 3), "ms_per_step_min": round(m["ms_min"], 3),
+        "ms_per_step_max": round(m["ms_max"], 3),
         "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": desc, "global_batch": len(w.cams), "rays": len(w.cams) * w.cams[0].width *
                    w.cams[0].height},

@@ -352,7 +352,11 @@ __device__ bool seq_sample(const AccelView &av, const Frames &fr, const void *pa
 // in primitive-id order within each group of pairs with the same first sample.
 constexpr int kWin = 12;
 
-template <bool BF16, bool FADE>
+// OPAQUE_J (used where the kernel also runs the pairs pass and is short of
+// registers): the window start is hidden from loop-invariant code motion, so
+// the window's sample times are recomputed for each pair instead of being held
+// in about two dozen registers across the pair loop.  Same arithmetic either way.
+template <bool BF16, bool FADE, bool OPAQUE_J>
 __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay, const float *fade, uint32_t seg,
                           int stride, int n, const Dir &d, RayState &st) {
   const float dt = av.step, lim = 1.0f - av.eps;
@@ -383,11 +387,13 @@ __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay
       if (!fr.lds) ++st.n_pab;
       const size_t kb = (size_t)prim_of(A) * M3;
       int cur = -1;
+      int Jp = J;
+      if (OPAQUE_J) asm volatile("" : "+v"(Jp));
       float4 v[8];
 #pragma unroll
       for (int w = 0; w < kWin; ++w) {
         if (w >= lo && w <= hi) {
-          const float tau = (float)(J + w) * dt;
+          const float tau = (float)(Jp + w) * dt;
           const Cell c = locate(A, B, tau, M, hM);
           if (c.idx != cur) {
             load_corners<BF16>(pay, kb + c.idx, M, v);
@@ -512,7 +518,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3)
     pixel_ray(av.cams[v], px, py, d);
 #pragma unroll
     for (int i = 0; i < 3; ++i) s_dir[i][threadIdx.x] = d[i];
-    march_ray<BF16, FADE>(av, fr, pay, s_fade, (uint32_t)av.ray_seg[ray], tile_ray_count(av, tile), av.ray_nj[ray].x,
+    march_ray<BF16, FADE, BUILD>(av, fr, pay, s_fade, (uint32_t)av.ray_seg[ray], tile_ray_count(av, tile), av.ray_nj[ray].x,
                           Dir{&s_dir[0][threadIdx.x], kTileThreads}, st);
     if (bg) {   // composite over the background: I + (1 - A) B
       const float u = 1.0f - st.T;
