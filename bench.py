@@ -200,6 +200,11 @@ class Runner:
                 self.target = torch.rand((V, H, W, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(107))
             else:
                 self.target = torch.from_numpy(target).cuda()
+            # d MSE / d I = (2 / n) (I - target) on the colour channels, 0 on alpha:
+            # (rgba - [target, 0]) * [s, s, s, 0] in two elementwise kernels
+            self.target4 = torch.cat([self.target, torch.zeros_like(self.target[..., :1])], dim=-1).contiguous()
+            s = 2.0 / self.target.numel()
+            self.w4 = torch.tensor([s, s, s, 0.0], dtype=torch.float32, device="cuda")
             self.grads = {"payload": torch.zeros(self.dp.payload.shape, dtype=torch.float32, device="cuda"),
                           "pos": torch.zeros_like(self.dp.pos), "rot": torch.zeros_like(self.dp.rot),
                           "scale": torch.zeros_like(self.dp.scale)}
@@ -209,8 +214,7 @@ class Runner:
         acc = self.ctx.build_accel(self.dp, self.w.cams, self.w.params)
         rgba, aux = acc.render_fwd(self.dp, want_aux=self.backward)
         if self.backward:
-            g = self.torch.zeros_like(rgba)
-            g[..., :3] = (2.0 / self.target.numel()) * (rgba[..., :3] - self.target)   # d MSE / d I
+            g = self.torch.sub(rgba, self.target4).mul_(self.w4)   # d MSE / d I
             for v in self.grads.values():
                 v.zero_()
             acc.render_bwd(self.dp, aux, g, self.grads)

@@ -587,6 +587,12 @@ hipError_t launch_march_fwd(const AccelView &av, const mvp_prims &p, const float
 // weight (1 - T_{S-1}) / sigma_S < dt in place of dt and the colour adjoint is
 // at most |g|_inf (sum rule: (1 - T_{S-1}) sigma_k / sigma_S <= 1; sequential:
 // 1 - T* <= 1).
+// Rays per workgroup of k_bwd_rays (4 per thread).  Only the clamped rays
+// (about one in eight on a typical frame) replay a sample; they are gathered
+// in LDS first, so that the replay runs on full waves instead of on the few
+// lanes of every wave whose ray clamped.
+constexpr int kBwdRaysPerBlock = 1024;
+
 template <bool BF16, bool FADE>
 __global__ __launch_bounds__(256) void k_bwd_rays(AccelView av, const void *__restrict__ pay,
                                                   const mvp_ray_aux *__restrict__ aux,
@@ -596,27 +602,47 @@ __global__ __launch_bounds__(256) void k_bwd_rays(AccelView av, const void *__re
                                                   const uint32_t *__restrict__ pmax, float *__restrict__ g_bg,
                                                   size_t R) {
   extern __shared__ float s_fade[];
-  if (FADE) {
-    fill_fade(s_fade, av.M, av.fade_alpha, av.fade_beta);
-    __syncthreads();
-  }
-  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  const mvp_ray_aux ax = aux[r];
-  const float4 g = grad_rgba[r];
-  float tdot = g.w, wsig = 0.f;
-  if (bg) {
-    const float b0 = bg[3 * r], b1 = bg[3 * r + 1], b2 = bg[3 * r + 2];
-    tdot -= g.x * b0 + g.y * b1 + g.z * b2;
-    if (g_bg) {
+  __shared__ uint32_t s_clamped[kBwdRaysPerBlock];
+  __shared__ int s_nc;
+  if (threadIdx.x == 0) s_nc = 0;
+  if (FADE) fill_fade(s_fade, av.M, av.fade_alpha, av.fade_beta);
+  __syncthreads();
+  const float cmax = __uint_as_float(pmax[0]), smax = __uint_as_float(pmax[1]);
+  const size_t base = (size_t)blockIdx.x * kBwdRaysPerBlock;
+  // dL/dA of the ray (with a background, of the composite over it)
+  auto base_tdot = [&](size_t r, const float4 &g) {
+    float t = g.w;
+    if (bg) t -= g.x * bg[3 * r] + g.y * bg[3 * r + 1] + g.z * bg[3 * r + 2];
+    return t;
+  };
+  auto write = [&](size_t r, const float4 &g, float tdot, float wsig, int kstar, bool clamped) {
+    rc[r] = RayConst{tdot, wsig, kstar, 0};
+    const float g1 = fabsf(g.x) + fabsf(g.y) + fabsf(g.z);
+    const float gi = fmaxf(fabsf(g.x), fmaxf(fabsf(g.y), fabsf(g.z)));
+    rbd[r] = RayBound{av.step * (fabsf(tdot) + g1 * cmax + smax * gi), clamped ? gi : 0.f};
+  };
+  for (int o = 0; o < kBwdRaysPerBlock; o += 256) {
+    const size_t r = base + o + threadIdx.x;
+    if (r >= R) break;
+    const mvp_ray_aux ax = aux[r];
+    const float4 g = grad_rgba[r];
+    if (bg && g_bg) {
       const float u = 1.0f - rgba[r].w;
       g_bg[3 * r] += u * g.x;
       g_bg[3 * r + 1] += u * g.y;
       g_bg[3 * r + 2] += u * g.z;
     }
+    if (ax.j_end >= 0 && ax.t_prev >= 0.f) s_clamped[atomicAdd(&s_nc, 1)] = (uint32_t)(o + threadIdx.x);
+    else write(r, g, base_tdot(r, g), 0.f, -1, false);
   }
-  int kstar = -1;
-  if (ax.j_end >= 0 && ax.t_prev >= 0.f) {
+  __syncthreads();
+  const int nc = s_nc;
+  for (int ci = threadIdx.x; ci < nc; ci += blockDim.x) {
+    const size_t r = base + s_clamped[ci];
+    const mvp_ray_aux ax = aux[r];
+    const float4 g = grad_rgba[r];
+    float tdot = base_tdot(r, g), wsig = 0.f;
+    int kstar = -1;
     // the ray's pairs open at its last sample, in increasing primitive id as
     // the forward visited them
     const float tau = (float)ax.j_end * av.step;
@@ -674,13 +700,8 @@ __global__ __launch_bounds__(256) void k_bwd_rays(AccelView av, const void *__re
       tdot = -(g.x * (c0 / sig) + g.y * (c1 / sig) + g.z * (c2 / sig));
       wsig = (1.0f - ax.t_prev) / sig;
     }
+    write(r, g, tdot, wsig, kstar, !av.combine || kstar >= 0);
   }
-  rc[r] = RayConst{tdot, wsig, kstar, 0};
-  const float cmax = __uint_as_float(pmax[0]), smax = __uint_as_float(pmax[1]);
-  const float g1 = fabsf(g.x) + fabsf(g.y) + fabsf(g.z);
-  const float gi = fmaxf(fabsf(g.x), fmaxf(fabsf(g.y), fabsf(g.z)));
-  const bool clamped = ax.j_end >= 0 && ax.t_prev >= 0.f && (!av.combine || kstar >= 0);
-  rbd[r] = RayBound{av.step * (fabsf(tdot) + g1 * cmax + smax * gi), clamped ? gi : 0.f};
 }
 
 // Largest colour and opacity magnitudes of the payload, as float bits in
@@ -1369,7 +1390,7 @@ hipError_t launch_march_bwd(const AccelView &av, const mvp_prims &p, int64_t n_i
     else
       hipLaunchKernelGGL((k_payload_bound<false>), dim3(pg), dim3(256), 0, s, p.payload, n_vox, pmax);
   }
-  const unsigned rb = (unsigned)((R + 255) / 256);
+  const unsigned rb = (unsigned)((R + kBwdRaysPerBlock - 1) / kBwdRaysPerBlock);
 #define MVP_RAYS(B, F)                                                                                        \
   hipLaunchKernelGGL((k_bwd_rays<B, F>), dim3(rb), dim3(256), fade_shm, s, av, p.payload, aux,               \
                      (const float4 *)grad_rgba, bg, (const float4 *)rgba, rc, rbd, pmax, g_bg, R)
