@@ -96,19 +96,23 @@ struct Cell {
 
 __device__ __forceinline__ Cell locate(const float4 &A, const float4 &B, float tau, int M, float hM) {
   const float y[3] = {fmaf(tau, B.x, A.x), fmaf(tau, B.y, A.y), fmaf(tau, B.z, A.z)};
-  const float top = (float)(M - 2);
+  const float top = (float)(M - 2), Mf = (float)M;
   Cell c;
+  float qf[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     // u is in [0, M-1] (fma(-1, hM, hM) is exactly 0), so the lower corner is
     // floor(u), except u = M-1, which belongs to the last cell with offset 1
     const float yc = fminf(fmaxf(y[i], -1.0f), 1.0f);
     const float u = fmaf(yc, hM, hM);
-    const float qf = fminf(floorf(u), top);
-    c.i[i] = (int)qf;
-    c.f[i] = u - qf;
+    qf[i] = fminf(floorf(u), top);
+    c.i[i] = (int)qf[i];
+    c.f[i] = u - qf[i];
   }
-  c.idx = (c.i[2] * M + c.i[1]) * M + c.i[0];
+  // the index from the float coordinates: every term is an integer below 2^24
+  // (M <= 1024), so the two fused multiply-adds are exact, and they are full
+  // rate where a 32-bit integer multiply-add is not
+  c.idx = (int)fmaf(fmaf(qf[2], Mf, qf[1]), Mf, qf[0]);
   return c;
 }
 
@@ -978,7 +982,9 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
 #pragma unroll
           for (int ch = 0; ch < 4; ++ch) acc[q][ch] -= acc[q | bit][ch];
     if (gdst) {
-      const size_t fc = LDS_ACC ? (size_t)ci0 + (size_t)ci1 * lm.sy + (size_t)ci2 * lm.sz : (size_t)cell;
+      const size_t fc = LDS_ACC ? (size_t)((unsigned)ci0 + __umul24((unsigned)ci1, (unsigned)lm.sy) +
+                                           __umul24((unsigned)ci2, (unsigned)lm.sz))
+                                : (size_t)cell;
       flush_cell<LDS_ACC, FADE>(gdst, fc, M, lm, acc, wq, 0xffu, m, fxs);
     }
   }
