@@ -217,12 +217,17 @@ struct Dir {
 struct Frames {
   const float4 *lds;   // [4 * list length] or nullptr
   uint64_t lb;         // first culling-list entry of the tile
+  // S = 1: the frames are in LDS, S = 0: in device memory, S = -1: in LDS iff
+  // lds is set.  A fixed S keeps the LDS reads LDS instructions (a pointer that
+  // may point to either memory is read with flat loads, which also wait for
+  // every outstanding device-memory load).
+  template <int S = -1>
   __device__ __forceinline__ void local(const AccelView &av, int pos, const Dir &dir, float4 &A, float4 &B) const {
     float d[3];
     dir.get(d);
     float4 f0, f1, f2;
     int k;
-    if (lds) {
+    if (S == 1 || (S == -1 && lds)) {
       f0 = lds[4 * pos];
       f1 = lds[4 * pos + 1];
       f2 = lds[4 * pos + 2];
@@ -314,7 +319,7 @@ __device__ __forceinline__ int next_by_id(const AccelView &av, uint32_t seg, int
 // Sequential combine at sample j, whose summed step saturates: the
 // primitives containing j in increasing id, each with its own clamp step.
 // Returns true to stop.
-template <bool BF16, bool FADE>
+template <bool BF16, bool FADE, bool STAGED>
 __device__ bool seq_sample(const AccelView &av, const Frames &fr, const void *pay, const float *fade, uint32_t seg,
                            int stride, int n, const Dir &d, int j, RayState &st) {
   const float dt = av.step;
@@ -325,7 +330,7 @@ __device__ bool seq_sample(const AccelView &av, const Frames &fr, const void *pa
   for (int i = next_by_id(av, seg, stride, n, j, last); i < n; i = next_by_id(av, seg, stride, n, j, last)) {
     const int4 r = av.pr[seg + i * stride];
     float4 A, B;
-    fr.local(av, r.z, d, A, B);
+    fr.template local<STAGED ? 1 : 0>(av, r.z, d, A, B);
     const float4 s = sample_pair<BF16, FADE>(av, pay, fade, A, B, tau);
     const float Tn = st.T + s.w * dt;
     if (Tn <= 1.0f) {
@@ -356,11 +361,12 @@ __device__ bool seq_sample(const AccelView &av, const Frames &fr, const void *pa
 // in primitive-id order within each group of pairs with the same first sample.
 constexpr int kWin = 12;
 
-// OPAQUE_J (used where the kernel also runs the pairs pass and is short of
-// registers): the window start is hidden from loop-invariant code motion, so
+// OPAQUE_J (used where the kernel also runs the pairs pass or applies the fade
+// window, and is short of registers): the window start is hidden from
+// loop-invariant code motion, so
 // the window's sample times are recomputed for each pair instead of being held
 // in about two dozen registers across the pair loop.  Same arithmetic either way.
-template <bool BF16, bool FADE, bool OPAQUE_J>
+template <bool BF16, bool FADE, bool OPAQUE_J, bool STAGED>
 __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay, const float *fade, uint32_t seg,
                           int stride, int n, const Dir &d, RayState &st) {
   const float dt = av.step, lim = 1.0f - av.eps;
@@ -387,8 +393,8 @@ __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay
       const int lo = max(r.x, J) - J, hi = min(r.y, J1 - 1) - J;
       occ |= ((2u << hi) - 1u) & ~((1u << lo) - 1u);
       float4 A, B;
-      fr.local(av, r.z, d, A, B);
-      if (!fr.lds) ++st.n_pab;
+      fr.template local<STAGED ? 1 : 0>(av, r.z, d, A, B);
+      if (!STAGED) ++st.n_pab;
       const size_t kb = (size_t)prim_of(A) * M3;
       int cur = -1;
       int Jp = J;
@@ -435,7 +441,7 @@ __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay
           else stop = composite(st, J + w, as[w], ar[w], ag[w], ab[w], dt, lim);
         }
       }
-      if (wseq < kWin) stop = seq_sample<BF16, FADE>(av, fr, pay, fade, seg, stride, n, d, J + wseq, st);
+      if (wseq < kWin) stop = seq_sample<BF16, FADE, STAGED>(av, fr, pay, fade, seg, stride, n, d, J + wseq, st);
       w0 = wseq + 1;
     }
     if (stop) break;
@@ -495,7 +501,6 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3)
       ++n_stage;
     }
   }
-  const Frames fr{staged ? s_frm : nullptr, lb};
   int total;
   {
     size_t ray;
@@ -522,8 +527,11 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3)
     pixel_ray(av.cams[v], px, py, d);
 #pragma unroll
     for (int i = 0; i < 3; ++i) s_dir[i][threadIdx.x] = d[i];
-    march_ray<BF16, FADE, BUILD>(av, fr, pay, s_fade, (uint32_t)av.ray_seg[ray], tile_ray_count(av, tile), av.ray_nj[ray].x,
-                          Dir{&s_dir[0][threadIdx.x], kTileThreads}, st);
+    const uint32_t seg = (uint32_t)av.ray_seg[ray];
+    const int stride = tile_ray_count(av, tile), n = av.ray_nj[ray].x;
+    const Dir dir{&s_dir[0][threadIdx.x], kTileThreads};
+    if (staged) march_ray<BF16, FADE, BUILD || FADE, true>(av, Frames{s_frm, lb}, pay, s_fade, seg, stride, n, dir, st);
+    else march_ray<BF16, FADE, BUILD || FADE, false>(av, Frames{nullptr, lb}, pay, s_fade, seg, stride, n, dir, st);
     if (bg) {   // composite over the background: I + (1 - A) B
       const float u = 1.0f - st.T;
       st.I0 = fmaf(u, bg[3 * ray], st.I0);
