@@ -825,7 +825,7 @@ __device__ __forceinline__ void flush_cell(T *dst, size_t cell, int M, const Lds
 // voxel corners (registers while the samples stay in one cell, then gdst:
 // the LDS copy of k's gradient or device memory) and the pose chain of the
 // pair added to P (dL/dt 3, dL/dR 9 row-major, dL/ds 3).
-template <bool BF16, bool LDS_ACC, bool FADE, typename GAcc>
+template <bool BF16, bool LDS_ACC, bool FADE, bool PREFETCH, typename GAcc>
 __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__restrict__ rot,
                                          const float *__restrict__ scale, const void *__restrict__ pay,
                                          const mvp_ray_aux *__restrict__ aux, const float4 *__restrict__ grad_rgba,
@@ -876,19 +876,26 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
   // corner loads before the run and the flush after it are executed by the
   // wave's lanes together (a per-sample "cell changed" branch would issue them
   // once per lane, with the other lanes masked off).
+  // PREFETCH (where the registers allow it): the corners of a run are
+  // requested before the previous run's flush, so that their loads are in
+  // flight while the flush adds to LDS.
+  auto load_cell = [&](int cell) {
+    const ptrdiff_t b0 = (ptrdiff_t)(kb + cell) + so0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      cv[q] = Voxels<BF16>::load(pay, (size_t)(b0 + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0)));
+  };
   int j = jr.x;
   Cell c;
-  if (j <= jh) c = locate(A, B, (float)j * dt, M, hM);
+  if (j <= jh) {
+    c = locate(A, B, (float)j * dt, M, hM);
+    if (PREFETCH) load_cell(c.idx);
+  }
   while (j <= jh) {
     const int cell = c.idx;
     const int ci0 = c.i[0], ci1 = c.i[1], ci2 = c.i[2];
     ++runs;
-    {
-      const ptrdiff_t b0 = (ptrdiff_t)(kb + cell) + so0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        cv[q] = Voxels<BF16>::load(pay, (size_t)(b0 + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0)));
-    }
+    if (!PREFETCH) load_cell(cell);
     if (FADE) {
       const float wx[2] = {s_fade[ci0 + (mx ? 1 : 0)], s_fade[ci0 + (mx ? 0 : 1)]};
       const float wy[2] = {s_fade[ci1 + (my ? 1 : 0)], s_fade[ci1 + (my ? 0 : 1)]};
@@ -973,6 +980,7 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
       if (j > jh) break;
       c = locate(A, B, (float)j * dt, M, hM);
     } while (c.idx == cell);
+    if (PREFETCH && j <= jh) load_cell(c.idx);
     float acc[8][4];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -1277,7 +1285,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
           if (s_pre[mid] <= i) q = mid; else hi = mid - 1;
         }
         const uint2 rec = av.ent_rec[s_start[q] + (i - s_pre[q])];
-        bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, rec, s_gent[q >> 2], s_tile[q >> 2], k, gdst,
+        bwd_pair<BF16, LDS_ACC, FADE, WAVES == 1>(av, rot, scale, pay, aux, grad_rgba, rc, rec, s_gent[q >> 2], s_tile[q >> 2], k, gdst,
                                       lm, fscale, s_fade, pose, P, n_run);
         ++n_rep;
       }
@@ -1317,7 +1325,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
       for (uint32_t i = i0, q = q0; i < iend; i += stride) {
         while (s_pre[q + 1] <= i) ++q;
         const uint2 rec = av.ent_rec[s_start[q] + (i - s_pre[q])];
-        bwd_pair<BF16, LDS_ACC, FADE>(av, rot, scale, pay, aux, grad_rgba, rc, rec, s_gent[q >> 2], s_tile[q >> 2], k, gdst,
+        bwd_pair<BF16, LDS_ACC, FADE, WAVES == 1>(av, rot, scale, pay, aux, grad_rgba, rc, rec, s_gent[q >> 2], s_tile[q >> 2], k, gdst,
                                       lm, fscale, s_fade, pose, P, n_run);
         ++n_rep;
       }
