@@ -336,6 +336,11 @@ mvp_status mvp_poll(mvp_ctx *ctx, uint64_t ticket, int32_t *state, double *t_sub
  * device (0 until done).  Any pointer may be NULL. */
 mvp_status mvp_ticket_times(mvp_ctx *ctx, uint64_t ticket, double *t_submit, double *t_start,
                             double *t_done);
+/* Ray-samples and prim-samples (as mvp_accel_counts) that a done request's
+ * forward evaluated; either pointer may be NULL.  Unknown ticket:
+ * MVP_ERR_INVALID; queued, running or failed: MVP_ERR_NOT_READY.  (Both are 0
+ * if the library could not allocate the pinned block it copies them through.) */
+mvp_status mvp_ticket_samples(mvp_ctx *ctx, uint64_t ticket, uint64_t *ray_samples, uint64_t *prim_samples);
 /* The monotonic clock (seconds) of the serving stamps, so that a client can
  * measure latency from its own arrival times. */
 double mvp_clock(void);

@@ -88,6 +88,7 @@ _SIGS = {
     "mvp_clock": ([], C.c_double),
     "mvp_wait": ([P, C.c_uint64, C.c_double], C.c_int),
     "mvp_ticket_release": ([P, C.c_uint64], C.c_int),
+    "mvp_ticket_samples": ([P, C.c_uint64, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)], C.c_int),
 }
 EXPORTS = tuple(_SIGS)
 

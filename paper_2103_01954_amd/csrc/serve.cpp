@@ -39,6 +39,7 @@ class Server {
   mvp_status scene_release(uint64_t id);
   mvp_status submit(const mvp_request *r, uint64_t *ticket);
   mvp_status poll(uint64_t t, int32_t *state, double *ts, double *tstart, double *td);
+  mvp_status samples(uint64_t t, uint64_t *ray, uint64_t *prim);
   mvp_status wait(uint64_t t, double timeout_s);
   mvp_status ticket_release(uint64_t t);
   size_t budget() const { return budget_; }
@@ -54,6 +55,7 @@ class Server {
     mvp_request req{};
     int32_t state = 0;   // 0 queued, 1 running, 2 done, 3 failed
     double t_submit = 0, t_start = 0, t_done = 0;
+    uint64_t ray_samples = 0, prim_samples = 0;   // of the forward, once done
   };
   enum : int { kFree = 0, kBuilding = 1, kRunning = 2 };
   struct Slot {
@@ -64,6 +66,8 @@ class Server {
     bool waiting = false;              // its build waits for memory (mu_)
     std::atomic<bool> finished{false};
     double t_finish = 0;
+    uint64_t *h_counts = nullptr;      // pinned: the forward's ray- and prim-sample counts
+    uint64_t ray_samples = 0, prim_samples = 0;
     uint64_t ticket = 0;
     mvp_accel *accel = nullptr;
     size_t reserved = 0;
@@ -100,6 +104,7 @@ Server::Server(mvp_ctx *ctx, size_t budget, int n_slots) : ctx_(ctx), budget_(bu
     Slot &s = *slots_.back();
     s.srv = this;
     (void)hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+    s.h_counts = (uint64_t *)ctx->pinned.get();   // nullptr: the counts are reported as 0
   }
   (void)hipStreamCreateWithFlags(&copy_stream_, hipStreamNonBlocking);
   for (auto &s : slots_) {
@@ -125,6 +130,7 @@ Server::~Server() {
       if (s->accel) destroy_accel(ctx_, s->accel, s->stream);
       (void)hipStreamDestroy(s->stream);
     }
+    ctx_->pinned.put(s->h_counts);
   }
   for (auto &kv : scenes_) ctx_->arena.release_after(kv.second.blocks, copy_stream_);
   (void)hipStreamSynchronize(copy_stream_);
@@ -134,6 +140,9 @@ Server::~Server() {
 void Server::host_done(void *p) {
   Slot *s = (Slot *)p;
   s->t_finish = now_s();
+  // the copy of the counts was enqueued before this callback on the same stream
+  s->ray_samples = s->h_counts ? s->h_counts[0] : 0;
+  s->prim_samples = s->h_counts ? s->h_counts[1] : 0;
   s->finished.store(true);
   Server *srv = s->srv;
   { std::lock_guard<std::mutex> g(srv->mu_); }
@@ -159,6 +168,8 @@ bool Server::reap_locked() {
     if (it != tickets_.end()) {
       it->second.state = 2;
       it->second.t_done = s.t_finish;
+      it->second.ray_samples = s.ray_samples;
+      it->second.prim_samples = s.prim_samples;
       auto sc = scenes_.find(it->second.req.scene_id);
       if (sc != scenes_.end()) --sc->second.pending;
     }
@@ -240,6 +251,8 @@ void Server::work(Slot &slot) {
       if (e == hipSuccess)
         e = launch_march_fwd(a->view(prims.M), prims, nullptr, req.rgba_out, nullptr, a->counters, slot.stream,
                              a->pairs_pending.exchange(false) ? &a->po : nullptr);
+      if (e == hipSuccess && slot.h_counts)   // counters [0] ray-samples, [1] prim-samples of the forward
+        e = hipMemcpyAsync(slot.h_counts, a->counters, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, slot.stream);
       if (e == hipSuccess) e = hipLaunchHostFunc(slot.stream, &Server::host_done, &slot);
       if (e != hipSuccess) {
         set_error("launch failed: %s", hipGetErrorString(e));
@@ -396,6 +409,16 @@ mvp_status Server::poll(uint64_t t, int32_t *state, double *ts, double *tstart, 
   return MVP_OK;
 }
 
+mvp_status Server::samples(uint64_t t, uint64_t *ray, uint64_t *prim) {
+  std::lock_guard<std::mutex> g(mu_);
+  auto it = tickets_.find(t);
+  if (it == tickets_.end()) { set_error("unknown ticket %llu", (unsigned long long)t); return MVP_ERR_INVALID; }
+  if (it->second.state != 2) { set_error("ticket %llu is not done", (unsigned long long)t); return MVP_ERR_NOT_READY; }
+  if (ray) *ray = it->second.ray_samples;
+  if (prim) *prim = it->second.prim_samples;
+  return MVP_OK;
+}
+
 mvp_status Server::wait(uint64_t t, double timeout_s) {
   std::unique_lock<std::mutex> lk(mu_);
   const auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s);
@@ -470,6 +493,11 @@ mvp_status mvp_poll(mvp_ctx *ctx, uint64_t ticket, int32_t *state, double *t_sub
 mvp_status mvp_ticket_times(mvp_ctx *ctx, uint64_t ticket, double *t_submit, double *t_start, double *t_done) {
   if (!ctx || !ctx->server) { set_error("no serving state"); return MVP_ERR_INVALID; }
   return ctx->server->poll(ticket, nullptr, t_submit, t_start, t_done);
+}
+
+mvp_status mvp_ticket_samples(mvp_ctx *ctx, uint64_t ticket, uint64_t *ray_samples, uint64_t *prim_samples) {
+  if (!ctx || !ctx->server) { set_error("no serving state"); return MVP_ERR_INVALID; }
+  return ctx->server->samples(ticket, ray_samples, prim_samples);
 }
 
 double mvp_clock(void) { return now_s(); }

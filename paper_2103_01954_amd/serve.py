@@ -61,6 +61,13 @@ class Server:
                                                                   C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
 
+    def samples(self, ticket: int):
+        """(ray-samples, prim-samples) of a done ticket's forward (mvp_ticket_samples)."""
+        a, b = C.c_uint64(), C.c_uint64()
+        L.check("mvp_ticket_samples", self.ctx.lib.mvp_ticket_samples(self.ctx.handle, C.c_uint64(ticket),
+                                                                      C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def clock(self) -> float:
         return float(self.ctx.lib.mvp_clock())
 
@@ -81,6 +88,7 @@ class Result:
     overlapped: int             # requests whose [start, done] window overlaps another's
     service_ms: List[float]     # done - start of the build (time on a slot)
     pixels: List[int]           # the request's image size
+    ray_samples: List[int]      # ray-samples its forward evaluated
 
 
 def _run(srv: Server, sids, reqs, params, arrivals: Optional[np.ndarray]) -> Result:
@@ -91,7 +99,7 @@ def _run(srv: Server, sids, reqs, params, arrivals: Optional[np.ndarray]) -> Res
     is held back for want of one."""
     n = len(reqs)
     pending = {}
-    lat, lag, windows, serv, pix = [], [], [], [], []
+    lat, lag, windows, serv, pix, rs = [], [], [], [], [], []
     failed = 0
     t0 = srv.clock()
     i = 0
@@ -115,11 +123,12 @@ def _run(srv: Server, sids, reqs, params, arrivals: Optional[np.ndarray]) -> Res
                     windows.append((tst, td))
                     serv.append((td - tst) * 1e3)
                     pix.append(npx)
+                    rs.append(srv.samples(t)[0])
                 else:
                     failed += 1
                 srv.release(t)
         time.sleep(0.0002)
-    return Result(lat, srv.clock() - t0, n, failed, lag, count_overlapped(windows), serv, pix)
+    return Result(lat, srv.clock() - t0, n, failed, lag, count_overlapped(windows), serv, pix, rs)
 
 
 def count_overlapped(windows) -> int:
@@ -175,6 +184,7 @@ def poisson_benchmark(ctx: Context, n_requests: int = 1000, seed: int = 5, n_sce
         per_load.append({
             "load": load, "offered_fps": round(rate, 1),
             "achieved_fps": round((opened.n - opened.failed) / opened.wall_s, 1),
+            "achieved_msamples_s": round(sum(opened.ray_samples) / opened.wall_s / 1e6, 1),
             "p50_ms": round(float(np.percentile(lat, 50)), 3) if lat.size else None,
             "p99_ms": round(float(np.percentile(lat, 99)), 3) if lat.size else None,
             "submit_lag_p99_ms": round(float(np.percentile(lag, 99)), 3) if lag.size else None,
@@ -193,6 +203,7 @@ def poisson_benchmark(ctx: Context, n_requests: int = 1000, seed: int = 5, n_sce
         "requests_per_load": n_requests, "slots": slots, "budget_gib": budget_bytes / 2 ** 30,
         "capacity_fps": round(capacity, 1),
         "capacity_mpix_s": round(pixels / closed.wall_s / 1e6, 1),
+        "capacity_msamples_s": round(sum(closed.ray_samples) / closed.wall_s / 1e6, 1),
         "closed_loop_p50_ms": round(float(np.percentile(closed.latency_ms, 50)), 3) if closed.latency_ms else None,
         "load": head["load"], "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "per_load": per_load, "failed": failed,

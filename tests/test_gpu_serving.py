@@ -30,13 +30,14 @@ def _scene_pool_f32():
             scenes.noisy_sphere_scene(64, n=512, m=16, scale=0.12, empty_frac=0.7, bf16=False)]
 
 
-def _render_direct(ctx, host, cam, bf16=True):
+def _render_direct(ctx, host, cam, bf16=True, with_counts=False):
     dp = DevicePrims.from_host(host, bf16=bf16)
     acc = ctx.build_accel(dp, [cam], PARAMS)
     rgba, _ = acc.render_fwd(dp, want_aux=False)
     torch.cuda.synchronize()
+    counts = tuple(acc.counts())
     acc.destroy()
-    return rgba[0]
+    return (rgba[0], counts) if with_counts else rgba[0]
 
 
 @pytest.fixture(scope="module")
@@ -99,16 +100,20 @@ def test_alone_equals_mix_equals_direct(serving):
             si, cam = 2, cam_x
         o = torch.empty((cam.height, cam.width, 4), device="cuda")
         jobs.append((si, cam, o, srv.submit(sids[si], cam, PARAMS, o)))
-    windows = []
+    windows, served_counts = [], []
     for si, cam, o, t in jobs:
         assert srv.wait(t, 120) == L.MVP_OK
         _, t_start, t_done = srv.times(t)
         windows.append((t_start, t_done))
+        served_counts.append(srv.samples(t))
         srv.release(t)
     assert sum(1 for si, cam, _, _ in jobs if cam.width == 1920) > 0
     assert len({si for si, _, _, _ in jobs}) == len(sids)
-    for si, cam, o, _ in jobs:
-        assert torch.equal(o, _render_direct(ctx, hosts[si], cam)), (si, cam.width, cam.height)
+    for (si, cam, o, _), sc in zip(jobs, served_counts):
+        direct, counts = _render_direct(ctx, hosts[si], cam, with_counts=True)
+        assert torch.equal(o, direct), (si, cam.width, cam.height)
+        # the ray- and prim-samples the served forward reports are the direct render's
+        assert sc == counts and sc[0] > 0, (si, cam.width, cam.height, sc, counts)
     for i in (0, 13, 29):
         assert torch.equal(jobs[i][2], alone)
     overlapped = count_overlapped(windows)
