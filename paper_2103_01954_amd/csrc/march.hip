@@ -374,8 +374,9 @@ __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay
   const float hM = 0.5f * (float)(M - 1);
   const size_t M3 = (size_t)M * M * M;
   int e0 = 0;                  // pairs before e0 have ended before the window
-  int J = av.pr[seg].x;
+  int4 q0 = av.pr[seg];        // record e0
   ++st.n_pj;
+  int J = q0.x;
   while (true) {
     float as[kWin], ar[kWin], ag[kWin], ab[kWin];
     // samples of the window inside at least one primitive, and the number of
@@ -385,10 +386,14 @@ __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay
 #pragma unroll
     for (int w = 0; w < kWin; ++w) as[w] = ar[w] = ag[w] = ab[w] = 0.f;
     const int J1 = J + kWin;
+    int4 rn = q0;
     for (int i = e0; i < n; ++i) {
-      const int4 r = av.pr[seg + i * stride];
-      ++st.n_pj;
+      const int4 r = rn;
       if (r.x >= J1) break;
+      if (i + 1 < n) {   // the next record is in flight while this pair is marched
+        rn = av.pr[seg + (i + 1) * stride];
+        ++st.n_pj;
+      }
       if (r.y < J) continue;
       const int lo = max(r.x, J) - J, hi = min(r.y, J1 - 1) - J;
       occ |= ((2u << hi) - 1u) & ~((1u << lo) - 1u);
@@ -447,14 +452,13 @@ __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay
     if (stop) break;
     // next occupied sample: every pair in front of e0 ends before J1, and all
     // later pairs start no earlier than e0 does
-    while (e0 < n) {
+    while (q0.y < J1) {
+      if (++e0 == n) break;
+      q0 = av.pr[seg + e0 * stride];
       ++st.n_pj;
-      if (av.pr[seg + e0 * stride].y >= J1) break;
-      ++e0;
     }
     if (e0 == n) break;
-    J = max(J1, av.pr[seg + e0 * stride].x);
-    ++st.n_pj;
+    J = max(J1, q0.x);
   }
   if (n > 255) {   // the 8-bit per-sample counts may have wrapped: count the samples up to the last one
     uint32_t np = 0;
