@@ -565,7 +565,7 @@ __global__ __launch_bounds__(256) void k_tile_capacity(const uint32_t *__restric
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < ntile) {   // saturated, so that a product beyond 32 bits cannot wrap to a small capacity
     const uint64_t c = (uint64_t)tile_cnt[t] * (tile_rays_cnt ? tile_rays_cnt[t] : (uint32_t)kTileThreads);
-    cap[t] = (uint32_t)min<uint64_t>(c, 0xffffffffull);
+    cap[t] = c > 0xffffffffull ? 0xffffffffu : (uint32_t)c;   // integer compare (no FP64 on the device)
   }
 }
 
