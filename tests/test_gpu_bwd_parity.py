@@ -186,3 +186,24 @@ def test_work_item_beyond_the_ordering_buffer(mvp_ctx):
     gpu = _gpu_grads(acc, dp, aux, up.reshape(1, cam.height, cam.width, 4))
     _check(gpu, ref, 1e-4)
     acc.destroy()
+
+
+@pytest.mark.parametrize("combine", ["sum", "sequential"])
+def test_mostly_clamped_rays_on_a_ragged_view(mvp_ctx, combine):
+    """The per-ray pass gathers the clamped rays of each group of 1024 before
+    replaying them: a 45x31 view (1395 rays, a full group and a partial one;
+    tiles cut by both borders) of dense boxes, where most covered rays clamp."""
+    prims = scenes.random_box_scene(97, n=8, m=8, s_lo=0.3, s_hi=0.6)
+    prims.payload[..., 3] *= 6.0
+    cam = scenes.look_at_camera(np.random.default_rng(98), 45, 31)
+    params = scenes.MarchParams(1 / 128, 1e-6, combine=combine)
+    ref_fwd = oracle.render(prims, cam, params)
+    clamped, covered = int((ref_fwd["t_prev"] >= 0).sum()), int((ref_fwd["j_end"] >= 0).sum())
+    say(f"{combine}: {clamped} of {covered} covered rays clamp")
+    assert clamped > 300 and clamped > covered // 2
+    up = _upstream(ref_fwd["rgba"].shape, 99, ref_fwd["margin"])
+    _, ref = oracle.render_grad(prims, cam, params, up)
+    acc, dp, rgba, aux = gpu_forward(mvp_ctx, prims, [cam], params)
+    gpu = _gpu_grads(acc, dp, aux, up.reshape(1, cam.height, cam.width, 4))
+    _check(gpu, ref, 1e-4)
+    acc.destroy()
