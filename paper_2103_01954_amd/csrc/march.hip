@@ -910,35 +910,29 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
         cv[q].w *= wq[q];
       }
     }
-    // the cell's field in the monomial basis: f = sum_q cf[q] m_q with
-    // m_q = product of the offsets (x, y, z) named by the bits of q
-    float cf[8][4];
+    // The cell's field in the monomial basis: f = sum_q cf[q] m_q with m_q the
+    // product of the offsets (x, y, z) named by the bits of q.  The ray's
+    // upstream colour gradient g is fixed along the run, and every colour term
+    // of a sample (g . rgb, the colour adjoint ws g and its position
+    // derivative) involves the colours only through g . c: the run keeps
+    // gcf[q] = g . cf[q][rgb] and the opacity coefficients sf[q] (the basis
+    // change is linear, so gcf comes from the corners' g . c), and sums the
+    // colour adjoint as g times sum_s m_q ws.
+    float gcf[8], sf[8], bw[8], b3[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      cf[q][0] = cv[q].x;
-      cf[q][1] = cv[q].y;
-      cf[q][2] = cv[q].z;
-      cf[q][3] = cv[q].w;
+      gcf[q] = fmaf(g.z, cv[q].z, fmaf(g.y, cv[q].y, g.x * cv[q].x));
+      sf[q] = cv[q].w;
+      bw[q] = b3[q] = 0.f;
     }
 #pragma unroll
     for (int bit = 1; bit < 8; bit <<= 1)
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        if (q & bit)
-#pragma unroll
-          for (int ch = 0; ch < 4; ++ch) cf[q][ch] -= cf[q ^ bit][ch];
-    // The ray's upstream colour gradient g is fixed along the run, and every
-    // colour term of a sample (g . rgb, the colour adjoint ws g and its
-    // position derivative) involves the colours only through g . c: the run
-    // keeps gcf[q] = g . cf[q][rgb] and the opacity coefficients sf[q], and
-    // sums the colour adjoint as g times sum_s m_q ws.
-    float gcf[8], sf[8], bw[8], b3[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      gcf[q] = g.x * cf[q][0] + g.y * cf[q][1] + g.z * cf[q][2];
-      sf[q] = cf[q][3];
-      bw[q] = b3[q] = 0.f;
-    }
+        if (q & bit) {
+          gcf[q] -= gcf[q ^ bit];
+          sf[q] -= sf[q ^ bit];
+        }
     do {
       const float tau = (float)j * dt;
       const float fx = mx ? 1.0f - c.f[0] : c.f[0];
@@ -985,6 +979,16 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
       c = locate(A, B, (float)j * dt, M, hM);
     } while (c.idx == cell);
     if (PREFETCH && j <= jh) load_cell(c.idx);
+    // monomial adjoint -> corner adjoint (transpose of the basis change), on
+    // the two sums before the colour adjoint is spread over the channels
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (!(q & bit)) {
+          bw[q] -= bw[q | bit];
+          b3[q] -= b3[q | bit];
+        }
     float acc[8][4];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -993,14 +997,6 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
       acc[q][2] = g.z * bw[q];
       acc[q][3] = b3[q];
     }
-    // monomial adjoint -> corner adjoint (transpose of the basis change)
-#pragma unroll
-    for (int bit = 1; bit < 8; bit <<= 1)
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (!(q & bit))
-#pragma unroll
-          for (int ch = 0; ch < 4; ++ch) acc[q][ch] -= acc[q | bit][ch];
     if (gdst) {
       const size_t fc = LDS_ACC ? (size_t)((unsigned)ci0 + __umul24((unsigned)ci1, (unsigned)lm.sy) +
                                            __umul24((unsigned)ci2, (unsigned)lm.sz))
