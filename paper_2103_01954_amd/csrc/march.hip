@@ -873,6 +873,7 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
   const unsigned m = (LDS_ACC && kRotateFlush) ? (threadIdx.x & 7u) : 0u;
   const bool mx = m & 1u, my = (m >> 1) & 1u, mz = (m >> 2) & 1u;
   const float hMx = mx ? -hM : hM, hMy = my ? -hM : hM, hMz = mz ? -hM : hM;
+  const float offx = mx ? 1.0f : 0.0f, offy = my ? 1.0f : 0.0f, offz = mz ? 1.0f : 0.0f;
   const int MMi = M * M;
   const int so0 = (mx ? 1 : 0) + (my ? M : 0) + (mz ? MMi : 0);   // slot 0's voxel offset
   const int sx = mx ? -1 : 1, sy = my ? -M : M, sz = mz ? -MMi : MMi;
@@ -935,9 +936,9 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
         }
     do {
       const float tau = (float)j * dt;
-      const float fx = mx ? 1.0f - c.f[0] : c.f[0];
-      const float fy = my ? 1.0f - c.f[1] : c.f[1];
-      const float fz = mz ? 1.0f - c.f[2] : c.f[2];
+      // offsets, mirrored where the lane's axis is: |0 - f| = f, |1 - f| = 1 - f
+      // (0 <= f <= 1; the absolute value folds into the instructions that use it)
+      const float fx = fabsf(offx - c.f[0]), fy = fabsf(offy - c.f[1]), fz = fabsf(offz - c.f[2]);
       const float mxy = fx * fy, mxz = fx * fz, myz = fy * fz, mxyz = mxy * fz;
       const float mq[8] = {1.0f, fx, fy, mxy, fz, mxz, myz, mxyz};
       float gc = gcf[0], sg = sf[0];
@@ -960,14 +961,16 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
         bw[q] = fmaf(mq[q], ws, bw[q]);
         b3[q] = fmaf(mq[q], a3, b3[q]);
       }
-      // gradient with respect to y of the interpolant of the adjoint-weighted
-      // channels: al[q] = a . cf[q], d/dx of sum al[q] m_q, times dx/dy = hM
+      // gradient with respect to the cell offsets of the interpolant of the
+      // adjoint-weighted channels: al[q] = a . cf[q], d/dx of sum al[q] m_q
+      // (the factor dx/dy = hM, signed on mirrored axes, is applied to the
+      // pair's sums G and H)
       float al[8];
 #pragma unroll
       for (int q = 1; q < 8; ++q) al[q] = fmaf(ws, gcf[q], a3 * sf[q]);
-      const float gx = hMx * (al[1] + al[3] * fy + al[5] * fz + al[7] * myz);
-      const float gyv = hMy * (al[2] + al[3] * fx + al[6] * fz + al[7] * mxz);
-      const float gz = hMz * (al[4] + al[5] * fx + al[6] * fy + al[7] * mxy);
+      const float gx = fmaf(al[7], myz, fmaf(al[5], fz, fmaf(al[3], fy, al[1])));
+      const float gyv = fmaf(al[7], mxz, fmaf(al[6], fz, fmaf(al[3], fx, al[2])));
+      const float gz = fmaf(al[7], mxy, fmaf(al[6], fy, fmaf(al[5], fx, al[4])));
       G0 += gx;
       G1 += gyv;
       G2 += gz;
@@ -1007,7 +1010,7 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
   if (!pose) return;
   // y = A (o + tau d - t), A = diag(1/s) R^T; d is the unit pixel ray
   const DevCam &cam = av.cams[rv];
-  const float G[3] = {G0, G1, G2}, H[3] = {H0, H1, H2};
+  const float G[3] = {hMx * G0, hMy * G1, hMz * G2}, H[3] = {hMx * H0, hMy * H1, hMz * H2};
   float Am[9], t[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -1021,7 +1024,7 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
 #pragma unroll
   for (int i = 0; i < 3; ++i) sk[i] = scale[3 * (size_t)k + i];
 #pragma unroll
-  for (int m = 0; m < 3; ++m) P[m] -= Am[m] * G[0] + Am[3 + m] * G[1] + Am[6 + m] * G[2];
+  for (int m = 0; m < 3; ++m) P[m] -= fmaf(Am[6 + m], G[2], fmaf(Am[3 + m], G[1], Am[m] * G[0]));
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     float rp = 0.f;

@@ -74,9 +74,15 @@ def test_gradients_accumulate_and_null_groups_are_skipped(mvp_ctx):
     twice = acc.render_bwd(dp, aux, g, {k: v.clone() for k, v in once.items()})
     only_pos = acc.render_bwd(dp, aux, g, {"pos": torch.zeros_like(dp.pos)})
     torch.cuda.synchronize()
+    # FP32 sums: element-wise within 1e-5 of the group's largest value (the
+    # backward without a payload gradient runs another work-item variant, whose
+    # per-thread pose sums take the pairs in another order)
+    def close(a, b):
+        return (a - b).abs().max().item() <= 1e-5 * b.abs().max().item()
+
     for k in once:
-        assert torch.allclose(twice[k], 2 * once[k], rtol=1e-5, atol=1e-6)
-    assert torch.allclose(only_pos["pos"], once["pos"], rtol=1e-5, atol=1e-6)
+        assert close(twice[k], 2 * once[k]), k
+    assert close(only_pos["pos"], once["pos"])
     acc.destroy()
 
 
