@@ -374,7 +374,7 @@ __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay
   const float hM = 0.5f * (float)(M - 1);
   const size_t M3 = (size_t)M * M * M;
   int e0 = 0;                  // pairs before e0 have ended before the window
-  int4 q0 = av.pr[seg];        // record e0
+  int4 q0 = av.pr[seg];        // record e0, kept across windows: it opens the next window's pair loop
   ++st.n_pj;
   int J = q0.x;
   while (true) {
@@ -386,7 +386,7 @@ __device__ void march_ray(const AccelView &av, const Frames &fr, const void *pay
 #pragma unroll
     for (int w = 0; w < kWin; ++w) as[w] = ar[w] = ag[w] = ab[w] = 0.f;
     const int J1 = J + kWin;
-    int4 rn = q0;
+    int4 rn = q0;                // record i; record i + 1 is requested before pair i is marched
     for (int i = e0; i < n; ++i) {
       const int4 r = rn;
       if (r.x >= J1) break;
