@@ -5,6 +5,8 @@ of concurrent requests (the forward writes every pixel from one thread in a
 fixed order, so equality is bit-exact), and equal to the direct render; the
 BF16 served image agrees with the plain FP32 forward of the unrounded scene
 within the BF16 tolerance."""
+import ctypes as C
+
 import numpy as np
 import pytest
 import torch
@@ -137,6 +139,9 @@ def test_admission_under_a_tiny_budget():
         assert srv.wait(t, 120) == L.MVP_OK
     assert srv.wait(big, 120) == L.MVP_ERR_DEVICE
     assert srv.poll(big)[0] == 3
+    # a failed request has no sample counts; a done one has them
+    assert srv.ctx.lib.mvp_ticket_samples(ctx.handle, C.c_uint64(big), None, None) == L.MVP_ERR_NOT_READY
+    assert srv.samples(tickets[0])[0] > 0
     for c, o in zip(cams, outs):
         assert torch.equal(o, _render_direct(ctx, host, c))
     # more requests after the failure are still served
@@ -152,6 +157,8 @@ def test_admission_under_a_tiny_budget():
         assert srv.release_scene(sid) == L.MVP_OK
     with pytest.raises(L.MVPError):
         srv.poll(123456789)
+    with pytest.raises(L.MVPError):
+        srv.samples(123456789)
     # scenes larger than the budget are refused
     with pytest.raises(L.MVPError):
         srv.add_scene(DevicePrims.from_host(scenes.noisy_sphere_scene(64, n=4096, m=16, scale=0.05,
