@@ -827,15 +827,15 @@ __device__ __forceinline__ void flush_cell(T *dst, size_t cell, int M, const Lds
 
 // Replay one (ray, primitive k) pair backward: channel adjoints to the 8
 // voxel corners (registers while the samples stay in one cell, then gdst:
-// the LDS copy of k's gradient or device memory) and the pose chain of the
-// pair added to P (dL/dt 3, dL/dR 9 row-major, dL/ds 3).
+// the LDS copy of k's gradient or device memory) and the pair's pose sums
+// added to P (sum G 3, then o_m G_i + d_m H_i 9; see pose_from_sums).
 template <bool BF16, bool LDS_ACC, bool FADE, bool PREFETCH, typename GAcc>
 __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__restrict__ rot,
                                          const float *__restrict__ scale, const void *__restrict__ pay,
                                          const mvp_ray_aux *__restrict__ aux, const float4 *__restrict__ grad_rgba,
                                          const RayConst *__restrict__ rc, const uint2 rec, uint64_t gent, int tile,
                                          int k, GAcc *gdst, const LdsMap &lm, float fxs, const float *s_fade, bool pose,
-                                         float (&P)[15], uint32_t &runs) {
+                                         float (&P)[12], uint32_t &runs) {
   const int M = av.M;
   const float hM = 0.5f * (float)(M - 1);
   const size_t M3 = (size_t)M * M * M;
@@ -1008,36 +1008,47 @@ __device__ __forceinline__ void bwd_pair(const AccelView &av, const float *__res
     }
   }
   if (!pose) return;
-  // y = A (o + tau d - t), A = diag(1/s) R^T; d is the unit pixel ray
+  // y = A (o + tau d - t), A = diag(1/s) R^T, d the unit pixel ray.  The pose
+  // gradient is linear in the pair's sums G = sum dL/dy and H = sum tau dL/dy,
+  // and the primitive is the same for every pair of a work item, so the pair
+  // adds only sum G (P[0..2]) and o_m G_i + d_m H_i (P[3 + 3m + i]); the
+  // primitive's A, t, R and s are applied once per item (pose_from_sums).
   const DevCam &cam = av.cams[rv];
   const float G[3] = {hMx * G0, hMy * G1, hMz * G2}, H[3] = {hMx * H0, hMy * H1, hMz * H2};
-  float Am[9], t[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const float4 row = av.xf[3 * (size_t)k + i];
-    Am[3 * i] = row.x; Am[3 * i + 1] = row.y; Am[3 * i + 2] = row.z; t[i] = row.w;
-  }
-  const float p[3] = {cam.o[0] - t[0], cam.o[1] - t[1], cam.o[2] - t[2]};
-  float Rm[9], sk[3];
+    P[i] += G[i];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) Rm[i] = rot[9 * (size_t)k + i];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) sk[i] = scale[3 * (size_t)k + i];
-#pragma unroll
-  for (int m = 0; m < 3; ++m) P[m] -= fmaf(Am[6 + m], G[2], fmaf(Am[3 + m], G[1], Am[m] * G[0]));
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    float rp = 0.f;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      const float Pm = fmaf(p[m], G[i], d[m] * H[i]);
-      P[3 + 3 * m + i] += Pm / sk[i];
-      rp = fmaf(Rm[3 * m + i], Pm, rp);
-    }
-    P[12 + i] -= rp / (sk[i] * sk[i]);
+    for (int m = 0; m < 3; ++m) P[3 + 3 * m + i] = fmaf(cam.o[m], G[i], fmaf(d[m], H[i], P[3 + 3 * m + i]));
   }
 }
 
+// Output i (0-2 dL/dt, 3-11 dL/dR row-major, 12-14 dL/ds) of primitive k's
+// pose gradient from the sums of its pairs (bwd_pair): SG = sum G and
+// S[m][i] = sum (o_m G_i + d_m H_i).  With P_mi = S[m][i] - t_m SG_i:
+// dL/dt_m = -sum_i A_im SG_i, dL/dR_mi = P_mi / s_i,
+// dL/ds_i = -sum_m R_mi P_mi / s_i^2.
+__device__ __forceinline__ float pose_from_sums(const AccelView &av, const float *__restrict__ rot,
+                                                const float *__restrict__ scale, int k, const float *sums,
+                                                int i) {
+  float Am[9], t[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const float4 row = av.xf[3 * (size_t)k + r];
+    Am[3 * r] = row.x; Am[3 * r + 1] = row.y; Am[3 * r + 2] = row.z; t[r] = row.w;
+  }
+  if (i < 3) return -fmaf(Am[6 + i], sums[2], fmaf(Am[3 + i], sums[1], Am[i] * sums[0]));
+  if (i < 12) {
+    const int m = (i - 3) / 3, c = (i - 3) % 3;
+    return (sums[i] - t[m] * sums[c]) / scale[3 * (size_t)k + c];
+  }
+  const int c = i - 12;
+  const float sk = scale[3 * (size_t)k + c];
+  float rp = 0.f;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) rp = fmaf(rot[9 * (size_t)k + 3 * m + c], sums[3 + 3 * m + c] - t[m] * sums[c], rp);
+  return -rp / (sk * sk);
+}
 
 
 // Samples the backward replays for the pair of entry record rec (of a
@@ -1192,9 +1203,9 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
     } else {
       if (out.pay) gdst = out.pay + (size_t)k * M3 * 4;
     }
-    float P[15];
+    float P[12];   // the pose sums of this thread's pairs (see bwd_pair)
 #pragma unroll
-    for (int i = 0; i < 15; ++i) P[i] = 0.f;
+    for (int i = 0; i < 12; ++i) P[i] = 0.f;
     float bound = 0.f;   // largest bound of this thread's pairs, then of the item's
     float fscale = 1.0f;
     if (kSortPairs && total <= sort_cap) {
@@ -1335,7 +1346,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
     }
     if (pose) {
 #pragma unroll
-      for (int i = 0; i < 15; ++i) {
+      for (int i = 0; i < 12; ++i) {
         float x = P[i];
 #pragma unroll
         for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
@@ -1343,11 +1354,16 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
       }
     }
     __syncthreads();
-    if (pose && threadIdx.x < 15 && total > 0) {
+    if (pose && threadIdx.x < 12) {   // the item's sums (each thread reads and writes its own column)
       float x = 0.f;
 #pragma unroll
       for (int w = 0; w < THREADS / kWave; ++w) x += s_pose[w][threadIdx.x];
+      s_pose[0][threadIdx.x] = x;
+    }
+    __syncthreads();
+    if (pose && threadIdx.x < 15 && total > 0) {
       const int i = threadIdx.x;
+      const float x = pose_from_sums(av, rot, scale, k, s_pose[0], i);
       if (i < 3) {
         if (out.pos) unsafeAtomicAdd(out.pos + 3 * (size_t)k + i, x);
       } else if (i < 12) {
