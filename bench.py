@@ -148,10 +148,10 @@ def bwd_bytes(lc, dtype, pose=True):
     ordering pass 24 B (entry record 8, the ray's last sample 8, its bounds 8);
     per pair replayed 104 B (entry record 8, entry frame 48, aux 8, upstream
     gradient 16, ray constants 16, camera 8 of its origin and matrix, cached)
-    plus 80 B for the pose chain (position 16, rotation 36, scale 12, camera
-    16); per cell run one voxel-corner set (8 corners); per non-zero gradient
-    value added to device memory 4 B."""
-    return (lc["bwd_pairs_visited"] * 24 + lc["bwd_pairs_replayed"] * (104 + (80 if pose else 0))
+    plus 16 B for its pose sums (the camera origin; the primitive's pose is
+    read once per work item, not counted); per cell run one voxel-corner set
+    (8 corners); per non-zero gradient value added to device memory 4 B."""
+    return (lc["bwd_pairs_visited"] * 24 + lc["bwd_pairs_replayed"] * (104 + (16 if pose else 0))
             + lc["bwd_cell_runs"] * 8 * VOX[dtype] + lc["bwd_grad_flush"] * 4)
 
 
