@@ -152,6 +152,51 @@ __device__ __forceinline__ int blocked_tile(int s, int tiles_x, int tiles_y) {
   return v * T + (by * kTileBlock + q / wb) * tiles_x + bx * kTileBlock + q % wb;
 }
 
+// Number of times each view's schedule is halved (first by rows, then by
+// columns, alternately) so that the XCDs sharing a view get one part each:
+// log2(kXcd / V) for V < kXcd views, else 0.
+__host__ __device__ __forceinline__ int view_splits(int V) {
+  int l = 0;
+  while (l < 3 && (V << (l + 1)) <= kXcd) ++l;
+  return l;
+}
+
+// The march's schedule: the view's tiles cut by `levels` halvings into
+// rectangles (top before bottom, left before right), each visited in blocks as
+// blocked_tile does.  With the XCDs' contiguous shares of the schedule
+// (xcd_tile) each XCD then marches one rectangle: for two views, a quadrant
+// each, which for a scene centred in the view balances the XCDs' work where
+// full-width stripes do not (the middle stripes cover more of it).
+__device__ __forceinline__ int split_tile(int s, int tiles_x, int tiles_y, int levels) {
+  const int T = tiles_x * tiles_y;
+  const int v = s / T;
+  int r = s - v * T;
+  int x0 = 0, y0 = 0, w = tiles_x, h = tiles_y;
+  for (int l = 0; l < levels; ++l) {
+    if (!(l & 1)) {   // rows: top part first
+      const int h0 = (h + 1) / 2;
+      if (r < w * h0) {
+        h = h0;
+      } else {
+        r -= w * h0;
+        y0 += h0;
+        h -= h0;
+      }
+    } else {          // columns: left part first
+      const int w0 = (w + 1) / 2;
+      if (r < w0 * h) {
+        w = w0;
+      } else {
+        r -= w0 * h;
+        x0 += w0;
+        w -= w0;
+      }
+    }
+  }
+  const int lt = blocked_tile(r, w, h);
+  return v * T + (y0 + lt / w) * tiles_x + x0 + lt % w;
+}
+
 // Ray number t (0 <= t < 256, row-major in the 16x16 tile) of `tile`: its
 // slot, view and pixel.  Returns false if there is no such ray (a tile cut by
 // the image border, or a ray subset with fewer rays in the tile).

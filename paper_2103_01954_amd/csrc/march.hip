@@ -488,7 +488,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(3)
   extern __shared__ float s_fade[];   // [M] when FADE
   const int slot = xcd_tile(blockIdx.x, av.V * av.tiles_x * av.tiles_y);
   if (slot < 0) return;
-  const int tile = blocked_tile(slot, av.tiles_x, av.tiles_y);
+  const int tile = split_tile(slot, av.tiles_x, av.tiles_y, view_splits(av.V));
   if (BUILD) {
     tile_pairs(av, tile, po);
     __syncthreads();
