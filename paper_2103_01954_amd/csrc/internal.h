@@ -164,9 +164,10 @@ __host__ __device__ __forceinline__ int view_splits(int V) {
 // The march's schedule: the view's tiles cut by `levels` halvings into
 // rectangles (top before bottom, left before right), each visited in blocks as
 // blocked_tile does.  With the XCDs' contiguous shares of the schedule
-// (xcd_tile) each XCD then marches one rectangle: for two views, a quadrant
-// each, which for a scene centred in the view balances the XCDs' work where
-// full-width stripes do not (the middle stripes cover more of it).
+// (xcd_tile) each XCD then marches one compact rectangle (for two views, a
+// quadrant each) rather than a full-width stripe: its block rows are shorter,
+// so neighbouring block rows, which share primitives, follow each other
+// sooner in the XCD's L2.
 __device__ __forceinline__ int split_tile(int s, int tiles_x, int tiles_y, int levels) {
   const int T = tiles_x * tiles_y;
   const int v = s / T;
