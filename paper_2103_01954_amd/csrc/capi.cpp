@@ -314,7 +314,11 @@ static mvp_status launch_lists(const mvp_accel *ac) {
   if (e == hipSuccess) e = launch_prim_entry_count(a->tile_list, ne, a->prim_cnt, s2);
   if (e == hipSuccess) e = launch_scan_u32_u64(a->prim_cnt, a->prim_entry_off, N, a->scan_scratch, s2);
   if (e == hipSuccess) e = launch_prim_entry_place(av, a->rect, ne, a->prim_entry_off, a->prim_entries, s2);
-  if (e == hipSuccess) e = launch_item_count(a->prim_entry_off, a->N, a->item_entries, a->prim_cnt, s2);
+  if (e == hipSuccess)
+    e = launch_prim_order(a->rect, a->N, a->V, a->tiles_x, a->tiles_y, a->prim_key, a->prim_bcnt,
+                          a->prim_boff, a->scan_scratch, a->item_prim, s2);
+  if (e == hipSuccess)
+    e = launch_item_count(a->prim_entry_off, a->item_prim, a->N, a->item_entries, a->prim_cnt, s2);
   if (e == hipSuccess) e = launch_scan_u32_u64(a->prim_cnt, a->item_off, N, a->scan_scratch, s2);
   if (e == hipSuccess) e = hipEventRecord(a->lists, s2);
   if (e != hipSuccess) {
@@ -385,7 +389,7 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
   int4 *rect = nullptr;
   uint32_t *tile_cnt = nullptr, *cap = nullptr, *rcnt = nullptr, *depth = nullptr;
   uint8_t *scratch = nullptr;
-  const size_t sb = scan_scratch_bytes(std::max<size_t>(ntile, (size_t)N));
+  const size_t sb = scan_scratch_bytes(std::max<size_t>(std::max<size_t>(ntile, (size_t)N), (size_t)kPrimBuckets));
   if (admit) {
     const size_t base = n_views * sizeof(DevCam) + 3 * (size_t)N * 16 + 2 * (ntile + 1) * 8 + R * 16 + 16 +
                         kNumCounters * 8 + (size_t)n_views * N * 20 + 2 * ntile * 4 + sb + 10 * 256 +
@@ -486,11 +490,15 @@ mvp_status build_accel(mvp_ctx *ctx, const mvp_prims *prims, const mvp_camera *c
     MVP_CHECK(keep.get(&a->prim_entries, ntp));
     MVP_CHECK(keep.get(&a->prim_entry_off, (size_t)N + 1));
     MVP_CHECK(keep.get(&a->item_off, (size_t)N + 1));
+    MVP_CHECK(keep.get(&a->item_prim, N ? (size_t)N : 1));
     MVP_CHECK(keep.get(&a->ent_base, ntp));
     MVP_CHECK(keep.get(&a->ent_n, 4 * ntp));
     MVP_CHECK(keep.get(&a->ent_tile, ntp));
     MVP_CHECK(keep.get(&a->ent_rec, npc));
     MVP_CHECK(ltmp.get(&prim_cnt, (size_t)N + 1));
+    MVP_CHECK(ltmp.get(&a->prim_key, N ? (size_t)N : 1));
+    MVP_CHECK(ltmp.get(&a->prim_bcnt, (size_t)kPrimBuckets));
+    MVP_CHECK(ltmp.get(&a->prim_boff, (size_t)kPrimBuckets + 1));
   }
   av = a->view(2);
   MVP_HIP(launch_zero_u32(tile_cnt, ntile, s));

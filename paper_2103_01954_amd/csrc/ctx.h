@@ -105,6 +105,7 @@ struct mvp_accel {
   uint64_t *prim_entry_off = nullptr;
   uint32_t *prim_entries = nullptr;
   uint64_t *item_off = nullptr;
+  uint32_t *item_prim = nullptr;
   int64_t n_items_max = 0;             // upper bound on the backward work items
   int32_t item_entries = 64;           // culling-list entries per backward work item
   float4 *ef = nullptr;                // entry frames
@@ -136,6 +137,8 @@ struct mvp_accel {
   int4 *rect = nullptr;
   uint32_t *prim_cnt = nullptr;
   uint8_t *scan_scratch = nullptr;
+  uint32_t *prim_key = nullptr, *prim_bcnt = nullptr;   // the backward's primitive order (launch_prim_order)
+  uint64_t *prim_boff = nullptr;
   int64_t n_slots = 0;                 // rays: V*H*W (full frames) or the subset size
   int64_t *ray_pix = nullptr;          // subset only: pixel id of each ray slot
   uint64_t *tile_ray_off = nullptr;    // subset only
@@ -151,7 +154,7 @@ struct mvp_accel {
     v.step = params.step; v.eps = params.eps_early; v.t_near = params.t_near;
     v.fade_alpha = params.fade_alpha; v.fade_beta = params.fade_beta; v.combine = params.combine;
     v.cams = cams; v.xf = xf; v.tile_off = tile_off; v.tile_list = tile_list;
-    v.prim_entry_off = prim_entry_off; v.prim_entries = prim_entries; v.item_off = item_off;
+    v.prim_entry_off = prim_entry_off; v.prim_entries = prim_entries; v.item_off = item_off; v.item_prim = item_prim;
     v.item_entries = item_entries;
     v.ef = ef; v.pair_base = pair_base; v.ray_seg = ray_seg; v.ray_nj = ray_nj; v.pr = pr;
     v.ent_base = ent_base; v.ent_n = ent_n; v.ent_tile = ent_tile; v.ent_rec = ent_rec;

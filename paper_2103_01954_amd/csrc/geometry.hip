@@ -377,10 +377,61 @@ __global__ __launch_bounds__(256) void k_prim_entry_place(AccelView av, const in
   }
 }
 
-__global__ __launch_bounds__(256) void k_item_count(const uint64_t *__restrict__ off, int n, int per_item,
-                                                    uint32_t *__restrict__ cnt) {
+// Work items of the p-th primitive in the backward's order (prim[p]; the
+// identity when prim is null).
+__global__ __launch_bounds__(256) void k_item_count(const uint64_t *__restrict__ off, const uint32_t *__restrict__ prim,
+                                                    int n, int per_item, uint32_t *__restrict__ cnt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int k = prim ? (int)prim[p] : p;
+  cnt[p] = (uint32_t)((off[k + 1] - off[k] + per_item - 1) / per_item);
+}
+
+// The backward's order of the primitives: by screen position, so that
+// consecutive work items read the per-ray data of neighbouring rays.  A
+// primitive's key is the Morton code (6 bits a side) of the centre of its tile
+// rectangle in the first view that sees it (the last key if none does); the
+// primitives are counted into the kPrimBuckets keys, and scattered by key.
+// The order within a key follows the atomics and carries no meaning: the
+// order only schedules the work items.
+__global__ __launch_bounds__(256) void k_prim_key(const int4 *__restrict__ rect, int N, int V, int tiles_x,
+                                                  int tiles_y, uint32_t *__restrict__ key,
+                                                  uint32_t *__restrict__ cnt) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) cnt[k] = (uint32_t)((off[k + 1] - off[k] + per_item - 1) / per_item);
+  if (k >= N) return;
+  uint32_t kk = kPrimBuckets - 1;
+  for (int v = 0; v < V; ++v) {
+    const int4 r = rect[(size_t)v * N + k];
+    if (r.x <= r.z && r.y <= r.w) {
+      const uint32_t cx = (uint32_t)min(63, (int)(((int64_t)r.x + r.z) * 32 / max(tiles_x, 1)));
+      const uint32_t cy = (uint32_t)min(63, (int)(((int64_t)r.y + r.w) * 32 / max(tiles_y, 1)));
+      kk = 0;
+      for (int b = 0; b < 6; ++b) kk |= (((cx >> b) & 1u) << (2 * b)) | (((cy >> b) & 1u) << (2 * b + 1));
+      break;
+    }
+  }
+  key[k] = kk;
+  atomicAdd(&cnt[kk], 1u);
+}
+
+__global__ __launch_bounds__(256) void k_prim_scatter(const uint32_t *__restrict__ key, int N,
+                                                      unsigned long long *__restrict__ boff,
+                                                      uint32_t *__restrict__ prim) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < N) prim[atomicAdd(&boff[key[k]], 1ull)] = (uint32_t)k;
+}
+
+hipError_t launch_prim_order(const int4 *rect, int N, int V, int tiles_x, int tiles_y, uint32_t *key,
+                             uint32_t *bcnt, uint64_t *boff, void *scan_scratch, uint32_t *prim, hipStream_t s) {
+  if (N == 0) return hipSuccess;
+  hipError_t e = launch_zero_u32(bcnt, kPrimBuckets, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prim_key, dim3((N + 255) / 256), dim3(256), 0, s, rect, N, V, tiles_x, tiles_y, key, bcnt);
+  e = launch_scan_u32_u64(bcnt, boff, kPrimBuckets, scan_scratch, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prim_scatter, dim3((N + 255) / 256), dim3(256), 0, s, key, N, (unsigned long long *)boff,
+                     prim);
+  return hipGetLastError();
 }
 
 hipError_t launch_prim_entry_count(const uint32_t *tile_list, uint64_t n, uint32_t *cnt, hipStream_t s) {
@@ -396,11 +447,11 @@ hipError_t launch_prim_entry_place(const AccelView &av, const int4 *rect, uint64
   return hipGetLastError();
 }
 
-hipError_t launch_item_count(const uint64_t *prim_entry_off, int n_prim, int per_item, uint32_t *cnt,
-                             hipStream_t s) {
+hipError_t launch_item_count(const uint64_t *prim_entry_off, const uint32_t *prim, int n_prim, int per_item,
+                             uint32_t *cnt, hipStream_t s) {
   if (n_prim == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_item_count, dim3((n_prim + 255) / 256), dim3(256), 0, s, prim_entry_off, n_prim, per_item,
-                     cnt);
+  hipLaunchKernelGGL(k_item_count, dim3((n_prim + 255) / 256), dim3(256), 0, s, prim_entry_off, prim, n_prim,
+                     per_item, cnt);
   return hipGetLastError();
 }
 

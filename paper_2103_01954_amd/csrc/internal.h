@@ -85,7 +85,8 @@ struct AccelView {
   const uint32_t *tile_list;   // [n_tile_pairs]
   const uint64_t *prim_entry_off;  // [N+1]
   const uint32_t *prim_entries;    // [n_tile_pairs]
-  const uint64_t *item_off;        // [N+1]
+  const uint64_t *item_off;        // [N+1], over the primitives in the order item_prim
+  const uint32_t *item_prim;       // [N] the backward's order of the primitives
   const float4 *ef;            // [3 n_tile_pairs]
   const uint64_t *pair_base;   // [V*T+1]
   const uint64_t *ray_seg;     // [R]
@@ -317,8 +318,13 @@ hipError_t launch_tile_fill(const AccelView &av, const int4 *rect, uint32_t *cur
 hipError_t launch_prim_entry_count(const uint32_t *tile_list, uint64_t n, uint32_t *cnt, hipStream_t s);
 hipError_t launch_prim_entry_place(const AccelView &av, const int4 *rect, uint64_t n, const uint64_t *off,
                                    uint32_t *prim_entries, hipStream_t s);
-hipError_t launch_item_count(const uint64_t *prim_entry_off, int n_prim, int per_item, uint32_t *cnt,
-                             hipStream_t s);
+hipError_t launch_item_count(const uint64_t *prim_entry_off, const uint32_t *prim, int n_prim, int per_item,
+                             uint32_t *cnt, hipStream_t s);
+// the backward's order of the primitives (prim[N]) by screen position; key[N],
+// bcnt[kPrimBuckets], boff[kPrimBuckets + 1] and the scan scratch are temporaries
+constexpr int kPrimBuckets = 4096;
+hipError_t launch_prim_order(const int4 *rect, int N, int V, int tiles_x, int tiles_y, uint32_t *key,
+                             uint32_t *bcnt, uint64_t *boff, void *scan_scratch, uint32_t *prim, hipStream_t s);
 int backward_item_entries(int M);   // culling-list entries per backward work item (<= 64)
 // sort each segment [off[i], off[i+1]) of data (n_seg segments) ascending, or
 // with depth: each tile's culling list by (depth[v N + id], id)

@@ -1132,7 +1132,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
   __shared__ uint32_t s_wsum[kSub / kWave];
   __shared__ uint64_t s_gent[kItemEntries];
   __shared__ int s_tile[kItemEntries];
-  __shared__ int s_prim;
+  __shared__ int s_prim, s_pos;
   const int M = av.M;
   const size_t M3 = (size_t)M * M * M;
   const int nacc = (int)(M3 * 4);                 // gradient values of one primitive
@@ -1150,17 +1150,18 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WAVES))
   }
   const uint64_t n_items = av.item_off[av.N];
   for (uint64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-    if (threadIdx.x == 0) {   // primitive of the item: last p with item_off[p] <= it
+    if (threadIdx.x == 0) {   // primitive of the item: the p-th in item order, last p with item_off[p] <= it
       int lo = 0, hi = av.N - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (av.item_off[mid] <= it) lo = mid; else hi = mid - 1;
       }
-      s_prim = lo;
+      s_pos = lo;
+      s_prim = av.item_prim ? (int)av.item_prim[lo] : lo;
     }
     __syncthreads();
     const int k = s_prim;
-    const uint64_t chunk = it - av.item_off[k];
+    const uint64_t chunk = it - av.item_off[s_pos];
     const uint64_t eb = av.prim_entry_off[k] + chunk * (uint64_t)av.item_entries;
     const int nent = (int)min<uint64_t>((uint64_t)av.item_entries, av.prim_entry_off[k + 1] - eb);
     const int nsub = 4 * nent;
